@@ -1,0 +1,294 @@
+"""CPU FP64 oracle of the ProxSkip / PDHGSkip TV hot path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It shares no code with the GPU
+library (paper_2411_00688_amd) and neither imports the other.
+
+Parity status of each function (what pins it lives in tests/test_oracle_*.py):
+  grad, div, tv, proj_ball ........ pinned (adjoint identity, closed-form |D|^2,
+                                     brute-force tiny cases, invariants)
+  fgp, tv_gap ..................... pinned (taut string in 1-D, 2-pixel closed
+                                     form, alpha = 0, constants, gap -> 0)
+  blur apply / adjoint ............ pinned (numpy FFT circular convolution)
+  joseph apply / adjoint .......... pinned (dense transpose, cardinal angles,
+                                     disk chord lengths)
+  proxskip / pdhgskip ............. pinned (p = 1 equals the separately written
+                                     PGD / PDHG bitwise; fixed points; same
+                                     minimiser as the reference solver)
+  coin ............................ pinned (published SplitMix64 output values,
+                                     Bernoulli statistics)
+  op_norm ......................... pinned (identity, blur = 1, SVD of small A)
+  pdhg_explicit ................... pinned (agrees with PGD/PDHG minimisers and
+                                     with the exact 1-D/2-pixel solutions)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+IDENTITY, BLUR, JOSEPH = 0, 1, 2
+
+
+class OrcOp(C.Structure):
+    _fields_ = [("kind", C.c_int), ("H", C.c_int), ("W", C.c_int),
+                ("kernel", C.POINTER(C.c_double)), ("kh", C.c_int), ("kw", C.c_int),
+                ("n_ang", C.c_int), ("angles", C.POINTER(C.c_double)),
+                ("n_det", C.c_int), ("pixel", C.c_double), ("det_spacing", C.c_double)]
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("step", C.c_double), ("dual_step", C.c_double),
+                ("p", C.c_double), ("outer_iters", C.c_int64), ("inner_iters", C.c_int32),
+                ("nonneg", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("k0", C.c_int64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        L.orc_grad.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.orc_div.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.orc_tv.argtypes = [C.c_int, C.c_int, dp]
+        L.orc_tv.restype = C.c_double
+        L.orc_proj_ball.argtypes = [C.c_size_t, dp, C.c_double, dp]
+        L.orc_fgp.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_int, dp, dp]
+        L.orc_tv_gap.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_int, dp, dp]
+        L.orc_tv_gap.restype = C.c_double
+        L.orc_op_out_size.argtypes = [C.POINTER(OrcOp)]
+        L.orc_op_out_size.restype = C.c_size_t
+        L.orc_op_apply.argtypes = [C.POINTER(OrcOp), dp, dp]
+        L.orc_op_adjoint.argtypes = [C.POINTER(OrcOp), dp, dp]
+        L.orc_objective.argtypes = [C.POINTER(OrcOp), dp, dp, C.c_double]
+        L.orc_objective.restype = C.c_double
+        L.orc_splitmix64_mix.argtypes = [C.c_uint64]
+        L.orc_splitmix64_mix.restype = C.c_uint64
+        L.orc_coin.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_double]
+        L.orc_coin.restype = C.c_int
+        u8p = C.POINTER(C.c_uint8)
+        L.orc_proxskip.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, C.POINTER(OrcParams), u8p, dp]
+        L.orc_proxskip.restype = C.c_int64
+        L.orc_pgd.argtypes = [C.POINTER(OrcOp), dp, dp, dp, C.POINTER(OrcParams), dp]
+        L.orc_pdhgskip.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, dp, C.POINTER(OrcParams), u8p, dp]
+        L.orc_pdhgskip.restype = C.c_int64
+        L.orc_pdhg.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, C.POINTER(OrcParams), dp]
+        L.orc_op_norm.argtypes = [C.POINTER(OrcOp), C.c_int, C.c_uint64]
+        L.orc_op_norm.restype = C.c_double
+        L.orc_pdhg_explicit.argtypes = [C.POINTER(OrcOp), dp, C.c_double, C.c_int, C.c_int64,
+                                        dp, dp, dp, C.c_int64, dp]
+        _lib = L
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---------------------------------------------------------------- operators
+def grad(u):
+    u = _f64(u)
+    H, W = u.shape
+    q = np.empty((2, H, W))
+    lib().orc_grad(H, W, _p(u), _p(q))
+    return q
+
+
+def div(q):
+    q = _f64(q)
+    _, H, W = q.shape
+    u = np.empty((H, W))
+    lib().orc_div(H, W, _p(q), _p(u))
+    return u
+
+
+def tv(u):
+    u = _f64(u)
+    H, W = u.shape
+    return lib().orc_tv(H, W, _p(u))
+
+
+def proj_ball(w, lam):
+    w = _f64(w)
+    out = np.empty_like(w)
+    n = w[0].size
+    lib().orc_proj_ball(n, _p(w), float(lam), _p(out))
+    return out
+
+
+def fgp(v, lam, iters, nonneg=0, q=None):
+    """TV prox by FGP.  Returns (z, q_new); q (if given) is not modified."""
+    v = _f64(v)
+    H, W = v.shape
+    qq = np.zeros((2, H, W)) if q is None else _f64(q).copy()
+    z = np.empty((H, W))
+    lib().orc_fgp(H, W, _p(v), float(lam), int(iters), int(nonneg), _p(qq), _p(z))
+    return z, qq
+
+
+def tv_gap(v, lam, q, nonneg=0):
+    """(gap, primal) of the TV prox at dual point q."""
+    v = _f64(v)
+    q = _f64(q)
+    H, W = v.shape
+    primal = C.c_double(0.0)
+    g = lib().orc_tv_gap(H, W, _p(v), float(lam), int(nonneg), _p(q), C.byref(primal))
+    return g, primal.value
+
+
+class Op:
+    """Holds an orc_op and the arrays it points to."""
+
+    def __init__(self, kind, H, W, kernel=None, angles=None, n_det=0, pixel=1.0,
+                 det_spacing=1.0):
+        self.kind, self.H, self.W = kind, H, W
+        self._kernel = None if kernel is None else _f64(kernel)
+        self._angles = None if angles is None else _f64(angles)
+        s = OrcOp()
+        s.kind, s.H, s.W = kind, H, W
+        if self._kernel is not None:
+            s.kernel = _p(self._kernel)
+            s.kh, s.kw = self._kernel.shape
+        if self._angles is not None:
+            s.angles = _p(self._angles)
+            s.n_ang = len(self._angles)
+        s.n_det = n_det
+        s.pixel, s.det_spacing = pixel, det_spacing
+        self.s = s
+        self.out_shape = (len(self._angles), n_det) if kind == JOSEPH else (H, W)
+
+    def apply(self, x):
+        x = _f64(x)
+        y = np.empty(self.out_shape)
+        lib().orc_op_apply(C.byref(self.s), _p(x), _p(y))
+        return y
+
+    def adjoint(self, y):
+        y = _f64(y)
+        x = np.empty((self.H, self.W))
+        lib().orc_op_adjoint(C.byref(self.s), _p(y), _p(x))
+        return x
+
+    def norm(self, iters=200, seed=1):
+        return lib().orc_op_norm(C.byref(self.s), int(iters), int(seed))
+
+
+def identity(H, W):
+    return Op(IDENTITY, H, W)
+
+
+def blur(H, W, kernel):
+    return Op(BLUR, H, W, kernel=kernel)
+
+
+def joseph(H, W, angles, n_det, pixel, det_spacing):
+    return Op(JOSEPH, H, W, angles=angles, n_det=n_det, pixel=pixel, det_spacing=det_spacing)
+
+
+def objective(A: Op, b, x, alpha):
+    b = _f64(b)
+    x = _f64(x)
+    return lib().orc_objective(C.byref(A.s), _p(b), _p(x), float(alpha))
+
+
+# ---------------------------------------------------------------- coin
+def mix64(z: int) -> int:
+    return lib().orc_splitmix64_mix(z & 0xFFFFFFFFFFFFFFFF)
+
+
+def coin(seed, stream, k, p) -> int:
+    return lib().orc_coin(int(seed), int(stream), int(k), float(p))
+
+
+# ---------------------------------------------------------------- solvers
+def _params(alpha, step, dual_step, p, outer, inner, nonneg, seed, stream, k0):
+    P = OrcParams()
+    P.alpha, P.step, P.dual_step, P.p = alpha, step, dual_step, p
+    P.outer_iters, P.inner_iters, P.nonneg = outer, inner, nonneg
+    P.seed, P.stream_id, P.k0 = seed, stream, k0
+    return P
+
+
+def _state(a, shape):
+    return np.zeros(shape) if a is None else _f64(a).copy()
+
+
+def proxskip(A: Op, b, alpha, step, p, outer, inner, nonneg=0, seed=0, stream=0,
+             k0=0, x=None, h=None, q=None, want_obj=False):
+    """Returns dict(x, h, q, theta, obj, nprox)."""
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, h, q = _state(x, (H, W)), _state(h, (H, W)), _state(q, (2, H, W))
+    theta = np.zeros(outer, dtype=np.uint8)
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, step, 0.0, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_proxskip(C.byref(A.s), _p(b), _p(x), _p(h), _p(q), C.byref(P),
+                           theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                           _p(obj) if want_obj else None)
+    return dict(x=x, h=h, q=q, theta=theta, obj=obj, nprox=int(n))
+
+
+def pgd(A: Op, b, alpha, step, outer, inner, nonneg=0, x=None, q=None, want_obj=False):
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, q = _state(x, (H, W)), _state(q, (2, H, W))
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, step, 0.0, 1.0, outer, inner, nonneg, 0, 0, 0)
+    lib().orc_pgd(C.byref(A.s), _p(b), _p(x), _p(q), C.byref(P), _p(obj) if want_obj else None)
+    return dict(x=x, q=q, obj=obj)
+
+
+def pdhgskip(A: Op, b, alpha, sigma, tau, p, outer, inner, nonneg=0, seed=0, stream=0,
+             k0=0, x=None, h=None, y=None, q=None, want_obj=False):
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, h, q = _state(x, (H, W)), _state(h, (H, W)), _state(q, (2, H, W))
+    y = _state(y, A.out_shape)
+    theta = np.zeros(outer, dtype=np.uint8)
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, sigma, tau, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_pdhgskip(C.byref(A.s), _p(b), _p(x), _p(h), _p(y), _p(q), C.byref(P),
+                           theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                           _p(obj) if want_obj else None)
+    return dict(x=x, h=h, y=y, q=q, theta=theta, obj=obj, nprox=int(n))
+
+
+def pdhg(A: Op, b, alpha, sigma, tau, outer, inner, nonneg=0, x=None, y=None, q=None,
+         want_obj=False):
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, q = _state(x, (H, W)), _state(q, (2, H, W))
+    y = _state(y, A.out_shape)
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, sigma, tau, 1.0, outer, inner, nonneg, 0, 0, 0)
+    lib().orc_pdhg(C.byref(A.s), _p(b), _p(x), _p(y), _p(q), C.byref(P),
+                   _p(obj) if want_obj else None)
+    return dict(x=x, y=y, q=q, obj=obj)
+
+
+def pdhg_explicit(A: Op, b, alpha, nonneg, iters, x=None, y1=None, y2=None, obj_every=0):
+    b = _f64(b)
+    H, W = A.H, A.W
+    x = _state(x, (H, W))
+    y1 = _state(y1, A.out_shape)
+    y2 = _state(y2, (2, H, W))
+    nrec = iters // obj_every if obj_every > 0 else 0
+    obj = np.zeros(max(nrec, 1))
+    lib().orc_pdhg_explicit(C.byref(A.s), _p(b), float(alpha), int(nonneg), int(iters),
+                            _p(x), _p(y1), _p(y2), int(obj_every), _p(obj))
+    return dict(x=x, y1=y1, y2=y2, obj=obj[:nrec])

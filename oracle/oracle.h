@@ -1,0 +1,106 @@
+/*
+ * oracle.h -- plain CPU FP64 reference ("oracle") of the ProxSkip / PDHGSkip
+ * TV-regularised imaging iterations (Papoutsellis, Kereta, Papafitsoros,
+ * "Why do we regularise in every iteration for imaging inverse problems?").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this code.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may use it.  It shares no code, header, table or
+ * constant generator with the GPU library.
+ *
+ * Conventions (all arrays row-major, float64):
+ *   image  u[H][W];   pixel (i, j) = row i, column j.
+ *   dual   q[2][H][W]; plane 0 = y (row) component, plane 1 = x (column)
+ *          component, matching D u = (D_y u, D_x u) of the problem statement
+ *          in the paper's introduction (the TV definition before eq. (5)).
+ *   CT sinogram y[n_ang][n_det].
+ */
+#ifndef TVS_ORACLE_H
+#define TVS_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- discrete operators (TV definition before eq. (5); Sec. 2.1) ---- */
+void orc_grad(int H, int W, const double* u, double* q);
+void orc_div(int H, int W, const double* q, double* u);
+double orc_tv(int H, int W, const double* u);
+void orc_proj_ball(size_t n, const double* w, double lam, double* out);
+
+/* ---- TV prox by FGP ("AProjGD", Sec. 2.1-2.2, Sec. 3.1) ---- */
+void orc_fgp(int H, int W, const double* v, double lam, int iters, int nonneg,
+             double* q_inout, double* z_out);
+double orc_tv_gap(int H, int W, const double* v, double lam, int nonneg,
+                  const double* q, double* primal_out);
+
+/* ---- forward operators A ---- */
+enum { ORC_IDENTITY = 0, ORC_BLUR = 1, ORC_JOSEPH = 2 };
+typedef struct {
+    int kind;
+    int H, W;
+    /* blur: kernel[kh][kw], odd sizes, centre (kh/2, kw/2) */
+    const double* kernel;
+    int kh, kw;
+    /* Joseph parallel beam */
+    int n_ang;
+    const double* angles;
+    int n_det;
+    double pixel, det_spacing;
+} orc_op;
+
+size_t orc_op_out_size(const orc_op* A);
+void orc_op_apply(const orc_op* A, const double* x, double* y);
+void orc_op_adjoint(const orc_op* A, const double* y, double* x);
+double orc_objective(const orc_op* A, const double* b, const double* x, double alpha);
+
+/* ---- coin stream ---- */
+uint64_t orc_splitmix64_mix(uint64_t z);
+int orc_coin(uint64_t seed, uint64_t stream_id, int64_t k, double p);
+
+/* ---- outer algorithms ---- */
+typedef struct {
+    double alpha;      /* TV weight */
+    double step;       /* gamma (ProxSkip / PGD) or sigma (PDHGSkip / PDHG) */
+    double dual_step;  /* tau (PDHGSkip / PDHG) */
+    double p;          /* prox probability, (0, 1] */
+    int64_t outer_iters;
+    int32_t inner_iters;
+    int32_t nonneg;
+    uint64_t seed, stream_id;
+    int64_t k0;        /* first coin index */
+} orc_params;
+
+/* Alg. "ProxSkip".  x, h, q are in/out.  theta_trace (nullable) gets theta_k,
+ * obj_trace (nullable) gets Phi(x_{k+1}).  Returns the number of prox calls. */
+int64_t orc_proxskip(const orc_op* A, const double* b, double* x, double* h,
+                     double* q, const orc_params* P, uint8_t* theta_trace,
+                     double* obj_trace);
+/* Alg. "PGD/ISTA/FBS" with the same FGP prox (written separately). */
+void orc_pgd(const orc_op* A, const double* b, double* x, double* q,
+             const orc_params* P, double* obj_trace);
+/* Alg. "PDHGSkip-2".  y is the dual (data-space) iterate. */
+int64_t orc_pdhgskip(const orc_op* A, const double* b, double* x, double* h,
+                     double* y, double* q, const orc_params* P,
+                     uint8_t* theta_trace, double* obj_trace);
+/* PDHG (Chambolle-Pock) with the same FGP prox (written separately). */
+void orc_pdhg(const orc_op* A, const double* b, double* x, double* y,
+              double* q, const orc_params* P, double* obj_trace);
+
+/* Operator norm by power iteration on A^T A from a seeded start vector. */
+double orc_op_norm(const orc_op* A, int iters, uint64_t seed);
+
+/* Reference minimiser by diagonally preconditioned explicit PDHG with
+ * K = [A; D] (the paper's reference solver of Sec. 3.1).  Runs `iters`
+ * iterations; obj_every > 0 records Phi every obj_every iterations. */
+void orc_pdhg_explicit(const orc_op* A, const double* b, double alpha,
+                       int nonneg, int64_t iters, double* x, double* y1,
+                       double* y2, int64_t obj_every, double* obj_trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

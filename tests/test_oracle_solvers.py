@@ -1,0 +1,200 @@
+"""Pins of the oracle's outer algorithms and coin.
+
+ProxSkip at p = 1 must equal the separately written PGD bitwise (the paper:
+the two coincide only at p = 1, Sec. 2.1); PDHGSkip-2 at p = 1 must equal
+PDHG bitwise (Sec. 3.2: h vanishes and PDHG is recovered).  Fixed points,
+convergence to the same minimiser as an independent reference solver, the
+ProxSkip fixed-point relation h = grad f(x), Bernoulli statistics of the
+coin and bitwise resume.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_denoise(N=24, seed=3):
+    u, eta = synth.phantom_and_noise(N, N, 5, seed, (N, N))
+    return u, u + 0.05 * eta
+
+
+def small_ct(N=24, n_ang=18, n_det=35, seed=5):
+    u, eta = synth.phantom_and_noise(N, N, 5, seed, (n_ang, n_det))
+    A = O.joseph(N, N, synth.parallel_beam_angles(n_ang), n_det, 2.0 / N, 2.0 / N)
+    Au = A.apply(u)
+    return A, u, Au + 0.01 * Au.max() * eta
+
+
+def small_blur(N=20, seed=4):
+    u, eta = synth.phantom_and_noise(N, N, 5, seed, (N, N))
+    A = O.blur(N, N, synth.gaussian_blur_kernel(9, 2.0))
+    return A, u, A.apply(u) + 0.01 * eta
+
+
+# ---------------------------------------------------------------- p = 1
+@pytest.mark.parametrize("kind", ["identity", "blur", "ct"])
+def test_proxskip_p1_equals_pgd_bitwise(kind):
+    if kind == "identity":
+        _, b = small_denoise()
+        A = O.identity(*b.shape)
+        nonneg = 0
+    elif kind == "blur":
+        A, _, b = small_blur()
+        nonneg = 0
+    else:
+        A, _, b = small_ct()
+        nonneg = 1
+    step = 1.0 if kind != "ct" else 1.0 / A.norm(100) ** 2
+    r1 = O.proxskip(A, b, 0.08, step, 1.0, 12, 7, nonneg=nonneg, seed=9)
+    r2 = O.pgd(A, b, 0.08, step, 12, 7, nonneg=nonneg)
+    assert np.all(r1["theta"] == 1) and r1["nprox"] == 12
+    assert np.array_equal(r1["x"], r2["x"])
+    assert np.array_equal(r1["q"], r2["q"])
+
+
+@pytest.mark.parametrize("kind", ["identity", "ct"])
+def test_pdhgskip_p1_equals_pdhg_bitwise(kind):
+    if kind == "identity":
+        _, b = small_denoise()
+        A = O.identity(*b.shape)
+        nonneg = 0
+    else:
+        A, _, b = small_ct()
+        nonneg = 1
+    L = A.norm(100)
+    r1 = O.pdhgskip(A, b, 0.05, 1 / L, 1 / L, 1.0, 10, 6, nonneg=nonneg, seed=2)
+    r2 = O.pdhg(A, b, 0.05, 1 / L, 1 / L, 10, 6, nonneg=nonneg)
+    assert np.array_equal(r1["x"], r2["x"])
+    assert np.array_equal(r1["y"], r2["y"])
+    assert np.array_equal(r1["q"], r2["q"])
+
+
+# ---------------------------------------------------------------- fixed points
+def test_constant_image_is_a_fixed_point_bitwise():
+    c = np.full((16, 20), 0.42)
+    A = O.identity(16, 20)
+    r = O.proxskip(A, c, 0.1, 1.0, 0.3, 40, 10, seed=1, x=c)
+    assert np.array_equal(r["x"], c)
+    assert np.all(r["h"] == 0.0) and np.all(r["q"] == 0.0)
+    r = O.pdhgskip(A, c, 0.1, 1.0, 1.0, 0.3, 40, 10, seed=1, x=c, y=np.zeros_like(c))
+    assert np.array_equal(r["x"], c)
+
+
+def test_proxskip_converges_to_exact_denoising_solution():
+    """A = I, gamma = 1: the minimiser of eq. (5) is prox_{alpha TV}(b), here
+    from a long FGP run certified by its duality gap; ProxSkip at p = 0.3
+    reaches it, and at its fixed point h = grad f(x) = x - b."""
+    _, b = small_denoise()
+    alpha = 0.1
+    ustar, qs = O.fgp(b, alpha, 40000)
+    gap, primal = O.tv_gap(b, alpha, qs)
+    assert gap < 1e-10 * primal
+    A = O.identity(*b.shape)
+    r = O.proxskip(A, b, alpha, 1.0, 0.3, 3000, 100, seed=11)
+    phi = O.objective(A, b, r["x"], alpha)
+    phis = O.objective(A, b, ustar, alpha)
+    lower = phis - gap          # Phi* >= P(z_q) - gap
+    assert phi - lower <= 5e-8 * phis
+    # 1-strong convexity: |x - u*|^2 / 2 <= Phi(x) - Phi*
+    bound = math.sqrt(2 * max(phi - lower, 0)) + math.sqrt(2 * gap)
+    assert np.linalg.norm(r["x"] - ustar) <= bound + 1e-9
+    assert np.max(np.abs(r["h"] - (r["x"] - b))) < 1e-5
+
+
+def test_blur_proxskip_pgd_and_reference_solver_agree():
+    A, _, b = small_blur()
+    alpha = 0.02
+    ref = O.pdhg_explicit(A, b, alpha, 0, 60000)
+    r_pgd = O.pgd(A, b, alpha, 1.0, 3000, 30)
+    r_ps = O.proxskip(A, b, alpha, 1.0, 0.3, 6000, 30, seed=4)
+    phis = [O.objective(A, b, x, alpha) for x in (ref["x"], r_pgd["x"], r_ps["x"])]
+    assert max(phis) - min(phis) <= 1e-7 * min(phis)
+    assert np.max(np.abs(r_pgd["x"] - ref["x"])) < 1e-4
+    assert np.max(np.abs(r_ps["x"] - ref["x"])) < 1e-4
+
+
+def test_ct_pdhgskip_and_reference_solver_agree():
+    """Small non-negative CT problem: PDHGSkip-2 (p = 0.3), PDHG and the
+    diagonally preconditioned explicit PDHG reach one minimiser."""
+    A, _, b = small_ct()
+    alpha = 0.05
+    L = A.norm(200)
+    ref = O.pdhg_explicit(A, b, alpha, 1, 100000)
+    r_pd = O.pdhg(A, b, alpha, 1 / L, 1 / L, 4000, 30, nonneg=1)
+    r_sk = O.pdhgskip(A, b, alpha, 1 / L, 1 / L, 0.3, 8000, 30, nonneg=1, seed=8)
+    phis = [O.objective(A, b, x, alpha) for x in (ref["x"], r_pd["x"], r_sk["x"])]
+    assert max(phis) - min(phis) <= 1e-6 * min(phis)
+    assert np.min(ref["x"]) >= 0
+    scale = np.max(np.abs(ref["x"]))
+    assert np.max(np.abs(r_sk["x"] - ref["x"])) < 1e-3 * scale
+    # PDHGSkip fixed point: y = A x - b (dual optimality) and h = A^T y
+    assert np.max(np.abs(r_sk["y"] - (A.apply(r_sk["x"]) - b))) < 1e-4 * np.max(np.abs(b))
+    assert np.max(np.abs(r_sk["h"] - A.adjoint(r_sk["y"]))) < 1e-3 * np.max(np.abs(r_sk["h"]))
+
+
+# ---------------------------------------------------------------- resume
+def test_resume_is_bitwise():
+    _, b = small_denoise(16)
+    A = O.identity(16, 16)
+    full = O.proxskip(A, b, 0.1, 1.0, 0.3, 30, 5, seed=77, stream=3)
+    a = O.proxskip(A, b, 0.1, 1.0, 0.3, 13, 5, seed=77, stream=3)
+    bb = O.proxskip(A, b, 0.1, 1.0, 0.3, 17, 5, seed=77, stream=3, k0=13,
+                    x=a["x"], h=a["h"], q=a["q"])
+    assert np.array_equal(full["x"], bb["x"]) and np.array_equal(full["h"], bb["h"])
+    assert np.array_equal(full["theta"], np.concatenate([a["theta"], bb["theta"]]))
+
+
+# ---------------------------------------------------------------- coin
+def _thetas(seed, stream, K, p):
+    return np.array([O.coin(seed, stream, k, p) for k in range(K)])
+
+
+def test_coin_bernoulli_statistics():
+    K = 200000
+    for p in (0.05, 0.1, 0.5):
+        th = _thetas(123, 0, K, p)
+        m = th.sum()
+        sd = math.sqrt(K * p * (1 - p))
+        assert abs(m - K * p) < 4.5 * sd
+        # runs of ones: E = K p (1 - p) + p^2 ... use the number of 0->1
+        # transitions, expected (K - 1) p (1 - p), as an independence check
+        trans = np.sum((th[1:] == 1) & (th[:-1] == 0))
+        e = (K - 1) * p * (1 - p)
+        assert abs(trans - e) < 4.5 * math.sqrt(e)
+    # streams are not copies of each other
+    a, b = _thetas(5, 0, 4000, 0.5), _thetas(5, 1, 4000, 0.5)
+    agree = np.mean(a == b)
+    assert 0.45 < agree < 0.55
+
+
+def test_coin_edges():
+    assert all(O.coin(1, 2, k, 1.0) == 1 for k in range(1000))
+    assert O.coin(1, 2, 0, 0.0) == -1 and O.coin(1, 2, 0, 1.5) == -1
+    assert O.coin(1, 2, -1, 0.5) == -1
+    assert O.mix64(0) == 0
+
+
+def test_coin_counts_like_the_paper_table():
+    """The paper's prox counts are Binomial(iterations, p) draws of its own
+    coin; ours over the same iteration counts lands in the same range.
+    (The Dual-Huber row's mean of 215 over 30 runs is 8 standard errors below
+    5000 p = 238.4 and is not consistent with p = 0.04767; only our count is
+    checked there.)"""
+    rows = json.load(open(os.path.join(GOLDEN, "table1_prox_counts.json")))["rows"]
+    for row in rows:
+        K, p = row["iterations"], row["p"]
+        runs = row.get("runs", 1)
+        counts = [int(_thetas(2024, s, K, p).sum()) for s in range(runs)]
+        m = np.mean(counts)
+        sd = math.sqrt(K * p * (1 - p) / runs)
+        assert abs(m - K * p) <= 4 * sd + 1e-9
+        if runs == 1:
+            assert abs(row["prox_calls"] - K * p) <= 4 * sd + 1e-9
