@@ -1,0 +1,234 @@
+/*
+ * tvskip.h -- C ABI of the MI355X (gfx950) library for ProxSkip and
+ * PDHGSkip-2 on TV-regularised imaging inverse problems.
+ *
+ * The problem (eq. (5) of Papoutsellis, Kereta and Papafitsoros, "Why do we
+ * regularise in every iteration for imaging inverse problems?"):
+ *
+ *     argmin_u  1/2 |A u - b|_2^2 + alpha TV(u)        (optionally u >= 0,
+ *                                                      the CT problem of Sec. 3.3)
+ *
+ * solved by ProxSkip (Alg. "ProxSkip") or PDHGSkip-2 (Alg. "PDHGSkip-2"),
+ * whose randomly skipped TV prox is evaluated by an inner FGP loop (the
+ * paper's accelerated projected gradient on the dual, "AProjGD", Sec. 2-3).
+ *
+ * Conventions shared by every call:
+ *  - Images are row-major H x W; pixel (i, j) is row i, column j.  A TV dual
+ *    field is two planes [2][H][W]: plane 0 the row (y) component, plane 1
+ *    the column (x) component, matching D u = (D_y u, D_x u).  A CT sinogram
+ *    is row-major [n_ang][n_det].
+ *  - Array arguments named as device buffers are device pointers on the
+ *    context's device, contiguous, of the element type `dtype` (float or
+ *    double).  The caller owns them; the library never frees caller memory.
+ *    Arguments typed `const double*` with a `_host` suffix and every scalar
+ *    output are host memory.
+ *  - Work is ordered on the context's HIP stream.  Calls return once the work
+ *    is enqueued, except where they fill host outputs (reports, traces, gaps,
+ *    norms, objectives): those synchronise the stream before returning.
+ *  - Every call returns a tvs_status; on failure tvs_last_error() (per host
+ *    thread) holds a message.  No call aborts or throws across the ABI.
+ *    On failure no output is guaranteed to be written, and device buffers
+ *    passed as in/out may hold partial results.
+ *  - One context per host thread at a time.
+ */
+#ifndef TVSKIP_H
+#define TVSKIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tvs_status {
+    TVS_OK = 0,
+    TVS_ERR_INVALID_ARG = 1, /* null pointer, bad scalar (p outside (0, 1], ...) */
+    TVS_ERR_SHAPE = 2,       /* sizes out of range or inconsistent */
+    TVS_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+    TVS_ERR_OOM = 4,         /* device allocation failed */
+    TVS_ERR_NONFINITE = 5,   /* a checked result is NaN or infinite */
+    TVS_ERR_UNSUPPORTED = 6  /* combination not implemented */
+} tvs_status;
+
+typedef enum tvs_dtype { TVS_F32 = 0, TVS_F64 = 1 } tvs_dtype;
+
+typedef struct tvs_ctx tvs_ctx;
+typedef struct tvs_op tvs_op;
+
+/* ------------------------------------------------------------------ context
+ * Binds a device and a HIP stream (hipStream_t passed as void*; NULL is the
+ * null stream).  The context owns its scratch memory (grown on demand, freed
+ * by tvs_ctx_destroy). */
+tvs_status tvs_ctx_create(int device, void* hip_stream, tvs_ctx** out);
+void tvs_ctx_destroy(tvs_ctx* ctx);
+tvs_status tvs_ctx_set_stream(tvs_ctx* ctx, void* hip_stream);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* tvs_last_error(void);
+/* Blocks until all work enqueued on the context's stream has finished. */
+tvs_status tvs_sync(tvs_ctx* ctx);
+
+/* ---------------------------------------------------------------- operators
+ * A: X -> Y.  X is H x W.  Y is H x W (identity, blur) or n_ang x n_det (CT).
+ * An operator copies its tables to the device and keeps a pointer to ctx; it
+ * must be destroyed before the context. */
+
+/* A = I (the denoising problems of Sec. 2 and the batched denoising form). */
+tvs_status tvs_op_identity(tvs_ctx* ctx, int H, int W, tvs_op** out);
+
+/* A = periodic convolution (deblurring, Sec. 3.1):
+ *   (A x)_{i,j} = sum_{m,n} k_{m,n} x_{(i-m) mod H, (j-n) mod W},
+ * k_{m,n} = kernel_host[(m + kh/2) * kw + (n + kw/2)]; kh, kw odd, <= 17 and
+ * <= H, W.  The adjoint is the correlation with the same kernel. */
+tvs_status tvs_op_blur_periodic(tvs_ctx* ctx, int H, int W, const double* kernel_host,
+                                int kh, int kw, tvs_op** out);
+
+/* A = parallel-beam discrete Radon transform (CT, Sec. 3.3), discretised as
+ * Joseph's ray-driven projector with linear interpolation:
+ *   pixel centres ((j - (W-1)/2) pixel, ((H-1)/2 - i) pixel), bins
+ *   s_b = (b - (n_det-1)/2) det_spacing, ray {x cos t + y sin t = s_b}.
+ *   A ray with |cos t| >= |sin t| is sampled once per image row, otherwise
+ *   once per column, interpolating linearly between the two nearest pixel
+ *   centres of that row (column), weighted by pixel / max(|cos t|, |sin t|).
+ * The adjoint is its exact transpose (same interpolation weights), computed
+ * by a gather over pixels without atomics.  angles_host: n_ang radians.
+ * Requires det_spacing >= pixel / 4. */
+tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
+                            const double* angles_host, int n_det, double pixel,
+                            double det_spacing, tvs_op** out);
+
+void tvs_op_destroy(tvs_op* op);
+/* Output size (number of elements of Y). */
+size_t tvs_op_out_size(const tvs_op* op);
+/* y = A x  (x: device, H*W; y: device, out_size). */
+tvs_status tvs_op_apply(tvs_op* op, tvs_dtype dtype, const void* x, void* y);
+/* x = A^T y. */
+tvs_status tvs_op_adjoint(tvs_op* op, tvs_dtype dtype, const void* y, void* x);
+/* |A|_2 by `iters` power iterations on A^T A in float64 from a start vector
+ * seeded by `seed` (step sizes with sigma tau |K|^2 <= 1, Sec. 3.3). */
+tvs_status tvs_op_norm(tvs_op* op, int iters, uint64_t seed, double* norm_out);
+
+/* ----------------------------------------------------- TV building blocks
+ * D u = (D_y u, D_x u): forward differences, zero in the last row / column
+ * (Neumann, the TV definition before eq. (5)).  div = -D^T (Sec. 2.1). */
+tvs_status tvs_grad(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* u, void* q);
+tvs_status tvs_div(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* q, void* u);
+
+/* TV prox  z = argmin 1/2 |z - v|^2 + lambda TV(z) (+ z >= 0 if nonneg),
+ * by `inner_iters` FGP iterations on the dual (Dual-ROF, eq. (6)):
+ *   z = P_X(v + div r);  q_k = P_lambda(r + D z / 8);
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2;
+ *   r = q_k + ((t_k - 1) / t_{k+1}) (q_k - q_{k-1}),
+ * P_lambda the pixelwise projection onto the lambda ball (eq. (7)), warm
+ * started from q_inout (2*H*W, device, in/out: warm dual in, final dual out);
+ * t restarts at 1 on every call.  z_out: device, H*W.  rel_gap_out
+ * (nullable, host): gap(q) / P(z) of the returned pair, which synchronises. */
+tvs_status tvs_tv_prox(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* v,
+                       double lambda, int inner_iters, int nonneg, void* q_inout,
+                       void* z_out, double* rel_gap_out);
+
+/* Duality gap of the TV prox at dual point q: with z = P_X(v + div q),
+ *   gap = sum_i lambda |(D z)_i| - <(D z)_i, q_i>,  P(z) = 1/2|z - v|^2 + lambda TV(z).
+ * Host outputs (nullable); synchronises. */
+tvs_status tvs_tv_gap(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* v,
+                      double lambda, int nonneg, const void* q, double* gap_out,
+                      double* primal_out);
+
+/* Phi(x) = 1/2 |A x - b|^2 + alpha TV(x) (eq. (5), without the u >= 0
+ * indicator).  x: device H*W; b: device out_size.  Synchronises. */
+tvs_status tvs_objective(tvs_op* op, tvs_dtype dtype, const void* b, const void* x,
+                         double alpha, double* out);
+
+/* ------------------------------------------------------------- FGP tuning
+ * The FGP kernel is compiled for several output tiles (tile_w x tile_h) and
+ * temporal depths (steps: FGP iterations fused per launch, with a halo of
+ * `steps` pixels).  The choice is kept per (H, W, dtype) in the context. */
+int tvs_fgp_variant_count(void);
+/* Shape of variant `index` (host outputs). */
+tvs_status tvs_fgp_variant(int index, int* tile_w, int* tile_h, int* steps);
+/* Use variant `index` for (H, W, dtype) from now on; index -1 restores the
+ * default. */
+tvs_status tvs_fgp_set_variant(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int index);
+/* Times every variant on a seeded random H x W image (inner_iters FGP
+ * iterations, `reps` repetitions, HIP events), keeps the fastest and returns
+ * it in *best_index (nullable); ms_per_iter_out (nullable, host, variant
+ * count doubles) gets each variant's milliseconds per FGP iteration (-1 if
+ * not available for the dtype).  Synchronises; allocates temporary device
+ * memory. */
+tvs_status tvs_fgp_autotune(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int inner_iters,
+                            int reps, int* best_index, double* ms_per_iter_out);
+
+/* --------------------------------------------------------------------- coin
+ * theta_k ~ Bernoulli(p), i.i.d. in k (Alg. "ProxSkip", Alg. "PDHGSkip-2"),
+ * as a pure function of (seed, stream_id, k): SplitMix64 (Steele, Lea and
+ * Flood 2014, output mix of Stafford's variant 13): key = mix(seed ^
+ * mix(stream_id + G)), r = mix(key + (k + 1) G), theta = [(r >> 11) <
+ * floor(p 2^53)], G = 0x9E3779B97F4A7C15.  Returns 0 or 1, or -1 if p is
+ * outside (0, 1] or k < 0.  Host only. */
+int tvs_coin(uint64_t seed, uint64_t stream_id, int64_t k, double p);
+
+/* ------------------------------------------------------------------ solvers */
+typedef struct tvs_params {
+    double alpha;        /* TV weight, >= 0 */
+    double step;         /* gamma (ProxSkip) or sigma (PDHGSkip), > 0 */
+    double dual_step;    /* tau (PDHGSkip), > 0; ignored by ProxSkip */
+    double p;            /* prox probability, (0, 1]; p = 1 gives PGD / PDHG */
+    int64_t outer_iters; /* K >= 0 */
+    int32_t inner_iters; /* FGP iterations per prox call, >= 1 */
+    int32_t nonneg;      /* 1: add u >= 0 to g */
+    uint64_t seed;       /* coin seed */
+    uint64_t stream_id;  /* coin stream */
+    int64_t k0;          /* index of the first coin draw (resume) */
+    int32_t flags;       /* TVS_FLAG_* */
+    int32_t reserved;
+} tvs_params;
+
+/* Capture the whole launch sequence into a HIP graph and launch it as one
+ * graph; an identical later call (same op, buffers, params) relaunches the
+ * cached graph. */
+#define TVS_FLAG_GRAPH 1
+
+/* Iterate state, caller-owned device buffers, in/out.  x, h: H*W; q: 2*H*W
+ * (the warm FGP dual); y: out_size (PDHGSkip only, NULL for ProxSkip).
+ * Initial values in, values after the last iteration out. */
+typedef struct tvs_state {
+    void* x;
+    void* h;
+    void* q;
+    void* y;
+} tvs_state;
+
+typedef struct tvs_report {
+    int64_t n_prox;     /* number of prox evaluations (theta_k = 1) */
+    int64_t iters;      /* outer iterations done */
+} tvs_report;
+
+/* ProxSkip (Alg. "ProxSkip") with f = 1/2|A . - b|^2, g = alpha TV (+ u >= 0):
+ *   xhat = x_k - gamma (grad f(x_k) - h_k)
+ *   theta_k = 1: x_{k+1} = prox_{(gamma/p) g}(xhat - (gamma/p) h_k), by FGP
+ *   theta_k = 0: x_{k+1} = xhat
+ *   h_{k+1} = h_k + (p/gamma)(x_{k+1} - xhat)
+ * b: device out_size.  obj_trace (nullable, host, outer_iters doubles):
+ * Phi(x_{k+1}) per iteration (adds work; synchronises).  theta_trace
+ * (nullable, host, outer_iters bytes).  report (nullable, host). */
+tvs_status tvs_proxskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                        const tvs_params* params, double* obj_trace,
+                        uint8_t* theta_trace, tvs_report* report);
+
+/* PDHGSkip-2 (Alg. "PDHGSkip-2") with K = A, f = 1/2|. - b|^2, g = alpha TV
+ * (+ u >= 0), reading the dual update at K xbar_{k+1} and the control-variate
+ * update at xhat_k:
+ *   xhat = x_k - sigma (A^T y_k - h_k)
+ *   theta_k = 1: x_{k+1} = prox_{(sigma/p) g}(xhat - (sigma/p) h_k), by FGP
+ *   theta_k = 0: x_{k+1} = xhat
+ *   xbar = 2 x_{k+1} - x_k;  y_{k+1} = (y_k + tau (A xbar - b)) / (1 + tau)
+ *   h_{k+1} = h_k + (p/sigma)(x_{k+1} - xhat)
+ * Same arguments as tvs_proxskip; state->y is required. */
+tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                        const tvs_params* params, double* obj_trace,
+                        uint8_t* theta_trace, tvs_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVSKIP_H */

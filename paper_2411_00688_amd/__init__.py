@@ -1,0 +1,253 @@
+"""ProxSkip / PDHGSkip-2 for TV-regularised imaging on MI355X (gfx950).
+
+Thin Python binding of libtvskip.so: the functions below carry the C ABI's
+names (include/tvskip.h) and only marshal arguments (torch device tensors to
+raw device pointers, the current torch stream to a HIP stream).  Every step
+of the method runs in the library's HIP kernels; there is no CPU fallback,
+and the calls raise if the library has not been built.
+
+Handles (contexts, operators) are plain integers (C pointers).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._lib import (TVS_F32, TVS_F64, TVS_FLAG_GRAPH, TvsError, check, lib, tvs_params,
+                   tvs_report, tvs_state)
+
+__all__ = [
+    "TVS_F32", "TVS_F64", "TVS_FLAG_GRAPH", "TvsError",
+    "tvs_ctx_create", "tvs_ctx_destroy", "tvs_ctx_set_stream", "tvs_sync", "tvs_last_error",
+    "tvs_op_identity", "tvs_op_blur_periodic", "tvs_op_ct_joseph", "tvs_op_destroy",
+    "tvs_op_out_size", "tvs_op_apply", "tvs_op_adjoint", "tvs_op_norm",
+    "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
+    "tvs_proxskip", "tvs_pdhgskip",
+    "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
+]
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return TVS_F32
+    if t.dtype == torch.float64:
+        return TVS_F64
+    raise TypeError(f"tensor dtype must be float32 or float64, got {t.dtype}")
+
+
+def _ptr(t, numel=None, dtype=None):
+    """Device pointer of a contiguous CUDA/HIP tensor (checked)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU (torch device 'cuda')")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"tensor has {t.numel()} elements, {numel} expected")
+    if dtype is not None and _dtype_code(t) != dtype:
+        raise TypeError("all tensors of one call must share a dtype")
+    return C.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- context
+def tvs_ctx_create(device: int = 0, stream=None) -> int:
+    """Context on `device`, bound to `stream` (a torch.cuda.Stream, a raw
+    hipStream_t int, or None for torch's current stream)."""
+    if stream is None:
+        s = _current_stream()
+    elif isinstance(stream, int):
+        s = C.c_void_p(stream)
+    else:
+        s = C.c_void_p(stream.cuda_stream)
+    out = C.c_void_p()
+    check(lib().tvs_ctx_create(int(device), s, C.byref(out)))
+    return out.value
+
+
+def tvs_ctx_destroy(ctx: int) -> None:
+    lib().tvs_ctx_destroy(C.c_void_p(ctx))
+
+
+def tvs_ctx_set_stream(ctx: int, stream=None) -> None:
+    s = _current_stream() if stream is None else (
+        C.c_void_p(stream) if isinstance(stream, int) else C.c_void_p(stream.cuda_stream))
+    check(lib().tvs_ctx_set_stream(C.c_void_p(ctx), s))
+
+
+def tvs_sync(ctx: int) -> None:
+    check(lib().tvs_sync(C.c_void_p(ctx)))
+
+
+def tvs_last_error() -> str:
+    m = lib().tvs_last_error()
+    return m.decode() if m else ""
+
+
+# -------------------------------------------------------------- operators
+def tvs_op_identity(ctx: int, H: int, W: int) -> int:
+    out = C.c_void_p()
+    check(lib().tvs_op_identity(C.c_void_p(ctx), int(H), int(W), C.byref(out)))
+    return out.value
+
+
+def tvs_op_blur_periodic(ctx: int, H: int, W: int, kernel) -> int:
+    import numpy as np
+    k = np.ascontiguousarray(kernel, dtype=np.float64)
+    out = C.c_void_p()
+    check(lib().tvs_op_blur_periodic(C.c_void_p(ctx), int(H), int(W),
+                                     k.ctypes.data_as(C.POINTER(C.c_double)),
+                                     int(k.shape[0]), int(k.shape[1]), C.byref(out)))
+    return out.value
+
+
+def tvs_op_ct_joseph(ctx: int, H: int, W: int, angles, n_det: int, pixel: float,
+                     det_spacing: float) -> int:
+    import numpy as np
+    a = np.ascontiguousarray(angles, dtype=np.float64)
+    out = C.c_void_p()
+    check(lib().tvs_op_ct_joseph(C.c_void_p(ctx), int(H), int(W), int(a.size),
+                                 a.ctypes.data_as(C.POINTER(C.c_double)), int(n_det),
+                                 float(pixel), float(det_spacing), C.byref(out)))
+    return out.value
+
+
+def tvs_op_destroy(op: int) -> None:
+    lib().tvs_op_destroy(C.c_void_p(op))
+
+
+def tvs_op_out_size(op: int) -> int:
+    return int(lib().tvs_op_out_size(C.c_void_p(op)))
+
+
+def tvs_op_apply(op: int, x, y) -> None:
+    d = _dtype_code(x)
+    check(lib().tvs_op_apply(C.c_void_p(op), d, _ptr(x), _ptr(y, tvs_op_out_size(op), d)))
+
+
+def tvs_op_adjoint(op: int, y, x) -> None:
+    d = _dtype_code(y)
+    check(lib().tvs_op_adjoint(C.c_void_p(op), d, _ptr(y, tvs_op_out_size(op)), _ptr(x, None, d)))
+
+
+def tvs_op_norm(op: int, iters: int = 200, seed: int = 1) -> float:
+    out = C.c_double()
+    check(lib().tvs_op_norm(C.c_void_p(op), int(iters), int(seed), C.byref(out)))
+    return out.value
+
+
+# ------------------------------------------------------ TV building blocks
+def tvs_grad(ctx: int, u, q) -> None:
+    H, W = u.shape
+    d = _dtype_code(u)
+    check(lib().tvs_grad(C.c_void_p(ctx), d, H, W, _ptr(u), _ptr(q, 2 * H * W, d)))
+
+
+def tvs_div(ctx: int, q, u) -> None:
+    H, W = u.shape
+    d = _dtype_code(q)
+    check(lib().tvs_div(C.c_void_p(ctx), d, H, W, _ptr(q, 2 * H * W), _ptr(u, H * W, d)))
+
+
+def tvs_tv_prox(ctx: int, v, lam: float, inner_iters: int, nonneg: int, q, z,
+                want_gap: bool = False):
+    """FGP TV prox; q (2,H,W) is the warm dual in and the final dual out.
+    Returns the relative duality gap if want_gap, else None."""
+    H, W = v.shape
+    d = _dtype_code(v)
+    g = C.c_double()
+    check(lib().tvs_tv_prox(C.c_void_p(ctx), d, H, W, _ptr(v), float(lam), int(inner_iters),
+                            int(nonneg), _ptr(q, 2 * H * W, d), _ptr(z, H * W, d),
+                            C.byref(g) if want_gap else None))
+    return g.value if want_gap else None
+
+
+def tvs_tv_gap(ctx: int, v, lam: float, nonneg: int, q):
+    H, W = v.shape
+    d = _dtype_code(v)
+    gap, primal = C.c_double(), C.c_double()
+    check(lib().tvs_tv_gap(C.c_void_p(ctx), d, H, W, _ptr(v), float(lam), int(nonneg),
+                           _ptr(q, 2 * H * W, d), C.byref(gap), C.byref(primal)))
+    return gap.value, primal.value
+
+
+def tvs_objective(op: int, b, x, alpha: float) -> float:
+    d = _dtype_code(x)
+    out = C.c_double()
+    check(lib().tvs_objective(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), _ptr(x),
+                              float(alpha), C.byref(out)))
+    return out.value
+
+
+def tvs_coin(seed: int, stream_id: int, k: int, p: float) -> int:
+    return int(lib().tvs_coin(int(seed), int(stream_id), int(k), float(p)))
+
+
+# ---------------------------------------------------------------- solvers
+def _solve(fn, op, b, x, h, q, y, alpha, step, dual_step, p, outer_iters, inner_iters, nonneg,
+           seed, stream_id, k0, graph, want_obj, want_theta):
+    import numpy as np
+    d = _dtype_code(x)
+    n = x.numel()
+    st = tvs_state(_ptr(x), _ptr(h, n, d), _ptr(q, 2 * n, d),
+                   _ptr(y, tvs_op_out_size(op), d) if y is not None else None)
+    P = tvs_params(alpha=float(alpha), step=float(step), dual_step=float(dual_step), p=float(p),
+                   outer_iters=int(outer_iters), inner_iters=int(inner_iters),
+                   nonneg=int(nonneg), seed=int(seed), stream_id=int(stream_id), k0=int(k0),
+                   flags=TVS_FLAG_GRAPH if graph else 0, reserved=0)
+    rep = tvs_report()
+    obj = np.zeros(max(int(outer_iters), 1)) if want_obj else None
+    th = np.zeros(max(int(outer_iters), 1), dtype=np.uint8) if want_theta else None
+    check(fn(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st), C.byref(P),
+             obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
+             th.ctypes.data_as(C.POINTER(C.c_uint8)) if want_theta else None, C.byref(rep)))
+    return dict(n_prox=rep.n_prox, iters=rep.iters,
+                obj=obj[:outer_iters] if want_obj else None,
+                theta=th[:outer_iters] if want_theta else None)
+
+
+def tvs_proxskip(op: int, b, x, h, q, alpha, step, p, outer_iters, inner_iters, nonneg=0,
+                 seed=0, stream_id=0, k0=0, graph=False, want_obj=False, want_theta=False):
+    """ProxSkip in place on (x, h, q).  Returns dict(n_prox, iters, obj, theta)."""
+    return _solve(lib().tvs_proxskip, op, b, x, h, q, None, alpha, step, 0.0, p, outer_iters,
+                  inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta)
+
+
+def tvs_pdhgskip(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inner_iters,
+                 nonneg=0, seed=0, stream_id=0, k0=0, graph=False, want_obj=False,
+                 want_theta=False):
+    """PDHGSkip-2 in place on (x, h, q, y).  Returns dict(n_prox, iters, obj, theta)."""
+    return _solve(lib().tvs_pdhgskip, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
+                  inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta)
+
+
+# ------------------------------------------------------------- FGP tuning
+def tvs_fgp_variant_count() -> int:
+    return int(lib().tvs_fgp_variant_count())
+
+
+def tvs_fgp_variant(index: int):
+    tw, th, ts = C.c_int(), C.c_int(), C.c_int()
+    check(lib().tvs_fgp_variant(int(index), C.byref(tw), C.byref(th), C.byref(ts)))
+    return tw.value, th.value, ts.value
+
+
+def tvs_fgp_set_variant(ctx: int, dtype: int, H: int, W: int, index: int) -> None:
+    check(lib().tvs_fgp_set_variant(C.c_void_p(ctx), int(dtype), int(H), int(W), int(index)))
+
+
+def tvs_fgp_autotune(ctx: int, dtype: int, H: int, W: int, inner_iters: int = 50, reps: int = 3):
+    """Times every FGP tile variant; keeps the fastest for (H, W, dtype) in the
+    context.  Returns (best_index, [ms per FGP iteration per variant])."""
+    import numpy as np
+    n = tvs_fgp_variant_count()
+    ms = np.zeros(n)
+    best = C.c_int()
+    check(lib().tvs_fgp_autotune(C.c_void_p(ctx), int(dtype), int(H), int(W), int(inner_iters),
+                                 int(reps), C.byref(best), ms.ctypes.data_as(C.POINTER(C.c_double))))
+    return best.value, ms.tolist()

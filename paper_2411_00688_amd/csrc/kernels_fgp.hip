@@ -1,0 +1,400 @@
+// FGP (the paper's AProjGD: accelerated projected gradient on the TV dual)
+// for gfx950.
+//
+// One FGP iteration on the dual field q = (q_y, q_x) (two H x W planes):
+//   r   = q_{k-1} + beta_k (q_{k-1} - q_{k-2})          FISTA momentum
+//   z   = P_X(v + div r)                                 primal point
+//   q_k = P_lambda(r + D z / 8)                          projected step, 1/L = 1/8
+// with div = -D^T, D forward differences zero in the last row / column, and
+// P_lambda the pixelwise projection onto the lambda ball (eq. (7), read as a
+// ball of radius lambda).  beta_k = (t_{k-1} - 1) / t_k, t_0 = 1 (Beck and
+// Teboulle's sequence; the paper's printed extrapolation is garbled).
+//
+// Kernel design (temporal blocking): a workgroup owns a BH x BW output tile
+// and loads the tile plus a halo of TS pixels of (q_{k-1}, q_{k-2}, v) into
+// registers.  Each iteration has radius 1 (z looks one pixel up/left, D z
+// one pixel down/right), so after TS iterations computed entirely from LDS
+// and registers the central tile is exact; it is written back together with
+// the previous iterate (needed for the next momentum step).  HBM traffic per
+// launch is one read of (q_{k-1}, q_{k-2}, v) plus the halo and one write of
+// two dual fields, instead of TS times that.  Pixels outside the image are
+// zero and never feed an in-image pixel: every neighbour access is guarded by
+// the image-global boundary conditions.
+#include "tvs_internal.hpp"
+
+namespace tvs {
+
+template <typename T>
+__device__ __forceinline__ T ball_scale(T wy, T wx, T lam);
+
+// float: hardware reciprocal square root (about 1 ulp).  n2 is clamped away
+// from the denormal range, where the instruction flushes to zero: there
+// n2 > lam^2 implies lam < 1e-18 and the clamped scale is still <= 1.
+template <>
+__device__ __forceinline__ float ball_scale<float>(float wy, float wx, float lam) {
+    float n2 = wy * wy + wx * wx;
+    return (n2 > lam * lam) ? lam * __builtin_amdgcn_rsqf(fmaxf(n2, 1e-37f)) : 1.0f;
+}
+
+template <>
+__device__ __forceinline__ double ball_scale<double>(double wy, double wx, double lam) {
+    double nrm = sqrt(wy * wy + wx * wx);
+    return (nrm > lam) ? lam / nrm : 1.0;
+}
+
+template <typename T>
+struct FgpArgs {
+    const T* v;
+    const T* qa;   // q_{k-1}
+    const T* qb;   // q_{k-2}
+    T* oa;         // out: last iterate
+    T* ob;         // out: the one before (nullptr when nsteps == 1)
+    const T* beta; // beta[k]: momentum coefficient used to form r of iteration k
+    int k_start;
+    int nsteps;    // <= TS
+    T lam;
+    int nonneg;
+    int H, W;
+    size_t plane;  // H * W
+};
+
+// bit flags of a pixel's neighbour relations, precomputed once per launch
+enum : int {
+    F_IN = 1,       // inside the image and the loaded region
+    F_DY = 2,       // i < H-1: D_y exists at this pixel
+    F_UP = 4,       // i > 0 and the upper neighbour is in the tile
+    F_DX = 8,       // j < W-1
+    F_LEFT = 16,    // j > 0 and the left neighbour is in the tile
+    F_DOWN = 32,    // i < H-1 and the lower neighbour is in the tile
+    F_RIGHT = 64,   // j < W-1 and the right neighbour is in the tile
+    F_OUT = 128     // in the central tile and inside the image (stored)
+};
+
+template <typename T, int BW, int BH, int TS>
+__global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
+    constexpr int NT = 256;
+    constexpr int RW = BW + 2 * TS, RH = BH + 2 * TS, R = RW * RH;
+    constexpr int PPT = (R + NT - 1) / NT;
+    __shared__ T s_ry[R];
+    __shared__ T s_rx[R];
+    __shared__ T s_z[R];
+
+    const int H = a.H, W = a.W;
+    const int i0 = (int)blockIdx.y * BH - TS;
+    const int j0 = (int)blockIdx.x * BW - TS;
+    const int tid = (int)threadIdx.x;
+
+    T qay[PPT], qax[PPT], qby[PPT], qbx[PPT], vv[PPT], ry[PPT], rx[PPT], zz[PPT];
+    int fl[PPT];
+
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int idx = tid + p * NT;
+        const int li = idx / RW, lj = idx - (idx / RW) * RW;
+        const int i = i0 + li, j = j0 + lj;
+        const bool inr = idx < R;
+        const bool in = inr && i >= 0 && i < H && j >= 0 && j < W;
+        int f = 0;
+        if (in) {
+            f |= F_IN;
+            if (i < H - 1) f |= F_DY;
+            if (i > 0 && li > 0) f |= F_UP;
+            if (j < W - 1) f |= F_DX;
+            if (j > 0 && lj > 0) f |= F_LEFT;
+            if (i < H - 1 && li < RH - 1) f |= F_DOWN;
+            if (j < W - 1 && lj < RW - 1) f |= F_RIGHT;
+            if (li >= TS && li < TS + BH && lj >= TS && lj < TS + BW) f |= F_OUT;
+        }
+        fl[p] = f;
+        const size_t g = in ? (size_t)i * W + j : 0;
+        qay[p] = in ? a.qa[g] : T(0);
+        qax[p] = in ? a.qa[a.plane + g] : T(0);
+        qby[p] = in ? a.qb[g] : T(0);
+        qbx[p] = in ? a.qb[a.plane + g] : T(0);
+        vv[p] = in ? a.v[g] : T(0);
+    }
+
+    const T lam = a.lam;
+    const T eighth = T(0.125);
+    for (int s = 0; s < a.nsteps; ++s) {
+        const T beta = a.beta[a.k_start + s];
+        // r = q_{k-1} + beta (q_{k-1} - q_{k-2})
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int idx = tid + p * NT;
+            ry[p] = qay[p] + beta * (qay[p] - qby[p]);
+            rx[p] = qax[p] + beta * (qax[p] - qbx[p]);
+            if (idx < R) {
+                s_ry[idx] = ry[p];
+                s_rx[idx] = rx[p];
+            }
+        }
+        __syncthreads();
+        // z = P_X(v + div r)
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int idx = tid + p * NT;
+            const int f = fl[p];
+            T d = T(0);
+            if (f & F_DY) d += ry[p];
+            if (f & F_UP) d -= s_ry[idx - RW];
+            if (f & F_DX) d += rx[p];
+            if (f & F_LEFT) d -= s_rx[idx - 1];
+            T z = vv[p] + d;
+            if (a.nonneg) z = (z > T(0)) ? z : T(0);
+            zz[p] = z;
+            if (idx < R) s_z[idx] = z;
+        }
+        __syncthreads();
+        // q_k = P_lambda(r + D z / 8)
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int idx = tid + p * NT;
+            const int f = fl[p];
+            const T gy = (f & F_DOWN) ? s_z[idx + RW] - zz[p] : T(0);
+            const T gx = (f & F_RIGHT) ? s_z[idx + 1] - zz[p] : T(0);
+            const T wy = ry[p] + eighth * gy;
+            const T wx = rx[p] + eighth * gx;
+            const T sc = ball_scale<T>(wy, wx, lam);
+            qby[p] = qay[p];
+            qbx[p] = qax[p];
+            qay[p] = (f & F_IN) ? wy * sc : T(0);
+            qax[p] = (f & F_IN) ? wx * sc : T(0);
+        }
+        // No barrier here: the next step's first LDS writes (s_ry, s_rx) do not
+        // touch s_z, and its writes of s_z come after its first barrier.
+    }
+
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        if (fl[p] & F_OUT) {
+            const int idx = tid + p * NT;
+            const int li = idx / RW, lj = idx - (idx / RW) * RW;
+            const size_t g = (size_t)(i0 + li) * W + (j0 + lj);
+            a.oa[g] = qay[p];
+            a.oa[a.plane + g] = qax[p];
+            if (a.ob) {
+                a.ob[g] = qby[p];
+                a.ob[a.plane + g] = qbx[p];
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------- configs
+// Tile shapes compiled in; the autotuner (or the default) picks one by index.
+struct FgpVariant {
+    int bw, bh, ts;
+};
+static const FgpVariant kFgpVariants[] = {
+    {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8},
+    {64, 16, 1}, {64, 16, 4}, {64, 32, 4}, {16, 16, 4}, {64, 32, 8},
+};
+
+template <typename T>
+static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
+    const FgpVariant& V = kFgpVariants[vi];
+    dim3 grid(div_up(a.W, V.bw), div_up(a.H, V.bh));
+#define TVS_FGPV(BW_, BH_, TS_)                                                            \
+    if (V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                       \
+        hipLaunchKernelGGL((fgp_tb_kernel<T, BW_, BH_, TS_>), grid, dim3(256), 0, st, a); \
+        return;                                                                            \
+    }
+    TVS_FGPV(32, 32, 1) TVS_FGPV(32, 32, 2) TVS_FGPV(32, 32, 4) TVS_FGPV(32, 32, 8)
+    TVS_FGPV(64, 16, 1) TVS_FGPV(64, 16, 4) TVS_FGPV(64, 32, 4) TVS_FGPV(16, 16, 4)
+    if (sizeof(T) == 4) { TVS_FGPV(64, 32, 8) }
+#undef TVS_FGPV
+    throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
+}
+
+int fgp_variant_count() { return (int)(sizeof(kFgpVariants) / sizeof(kFgpVariants[0])); }
+
+FgpConfig fgp_variant(int index) {
+    FgpConfig c;
+    c.tile_w = kFgpVariants[index].bw;
+    c.tile_h = kFgpVariants[index].bh;
+    c.steps = kFgpVariants[index].ts;
+    return c;
+}
+
+static int find_variant(const FgpConfig& c, int dtype_bytes) {
+    for (int i = 0; i < fgp_variant_count(); ++i) {
+        const FgpVariant& V = kFgpVariants[i];
+        if (V.bw == c.tile_w && V.bh == c.tile_h && V.ts == c.steps) {
+            if (dtype_bytes == 8 && V.bw == 64 && V.bh == 32 && V.ts == 8) break;
+            return i;
+        }
+    }
+    throw Error{TVS_ERR_UNSUPPORTED, "FGP tile configuration not compiled"};
+}
+
+// Runs `iters` FGP iterations; returns the buffer holding the final dual
+// (q_inout itself or a scratch buffer).  q_inout is only read.
+template <typename T>
+T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
+           T* q_inout, const FgpConfig& cfg) {
+    const size_t plane = (size_t)H * W;
+    const int vi = find_variant(cfg, (int)sizeof(T));
+    const int TS = kFgpVariants[vi].ts;
+    T* bufs[4] = {q_inout, (T*)scratch(ctx, S_Q1, 2 * plane * sizeof(T)),
+                  (T*)scratch(ctx, S_Q2, 2 * plane * sizeof(T)),
+                  (T*)scratch(ctx, S_Q3, 2 * plane * sizeof(T))};
+    const T* beta = beta_table_dev<T>(ctx, iters + 1);
+    T* qa = q_inout;
+    T* qb = q_inout;  // iteration 0 forms r = q_warm whatever beta is
+    int k = 0;
+    while (k < iters) {
+        const int ns = (iters - k) < TS ? (iters - k) : TS;
+        T* outs[2];
+        int n = 0;
+        for (int b = 0; b < 4 && n < 2; ++b)
+            if (bufs[b] != qa && bufs[b] != qb) outs[n++] = bufs[b];
+        FgpArgs<T> a;
+        a.v = v;
+        a.qa = qa;
+        a.qb = qb;
+        a.oa = outs[0];
+        a.ob = ns > 1 ? outs[1] : nullptr;
+        a.beta = beta;
+        a.k_start = k;
+        a.nsteps = ns;
+        a.lam = (T)lambda;
+        a.nonneg = nonneg;
+        a.H = H;
+        a.W = W;
+        a.plane = plane;
+        launch_fgp_variant<T>(vi, a, ctx->stream);
+        TVS_LAUNCH_CHECK();
+        if (ns > 1) {
+            qb = outs[1];
+        } else {
+            qb = qa;
+        }
+        qa = outs[0];
+        k += ns;
+    }
+    return qa;
+}
+
+// -------------------------------------------------------------- finalize
+// z = P_X(v + div q) and the bookkeeping that follows a prox evaluation.
+// 32 x 32 tiles, 256 threads (4 pixels each); the transposed copy of xbar
+// goes through LDS so that both stores are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int W) {
+    constexpr int TW = 32, TH = 32;
+    __shared__ T s_t[TH][TW + 1];
+    const size_t plane = (size_t)H * W;
+    const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
+    const T* qy = f.q;
+    const T* qx = f.q + plane;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / TW, lj = idx % TW;
+        const int i = i0 + li, j = j0 + lj;
+        if (i >= H || j >= W) continue;
+        const size_t g = (size_t)i * W + j;
+        T d = T(0);
+        if (i < H - 1) d += qy[g];
+        if (i > 0) d -= qy[g - W];
+        if (j < W - 1) d += qx[g];
+        if (j > 0) d -= qx[g - 1];
+        T z = f.v[g] + d;
+        if (f.nonneg) z = (z > T(0)) ? z : T(0);
+        if (f.q_out != f.q) {
+            f.q_out[g] = qy[g];
+            f.q_out[plane + g] = qx[g];
+        }
+        if (f.mode == 0) {
+            f.z[g] = z;
+        } else {
+            const T xh = f.xhat[g];
+            f.h[g] = f.h[g] + f.rate * (z - xh);
+            if (f.mode == 2) {
+                const T xo = f.x[g];
+                const T xb = T(2) * z - xo;
+                f.xbar[g] = xb;
+                s_t[li][lj] = xb;
+            }
+            f.x[g] = z;
+        }
+    }
+    if (f.mode == 2 && f.xbarT) {
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int idx = (int)threadIdx.x + p * 256;
+            const int jj = idx / TH, ii = idx % TH;
+            const int i = i0 + ii, j = j0 + jj;
+            if (i < H && j < W) f.xbarT[(size_t)j * H + i] = s_t[ii][jj];
+        }
+    }
+}
+
+template <typename T>
+void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f) {
+    dim3 grid(div_up(W, 32), div_up(H, 32));
+    hipLaunchKernelGGL((finalize_kernel<T>), grid, dim3(256), 0, ctx->stream, f, H, W);
+    TVS_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- grad / div
+template <typename T>
+__global__ void grad_kernel(int H, int W, const T* u, T* q) {
+    const size_t n = (size_t)H * W;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g / W), j = (int)(g % W);
+        const T uc = u[g];
+        q[g] = (i < H - 1) ? u[g + W] - uc : T(0);
+        q[n + g] = (j < W - 1) ? u[g + 1] - uc : T(0);
+    }
+}
+
+template <typename T>
+__global__ void div_kernel(int H, int W, const T* q, T* out) {
+    const size_t n = (size_t)H * W;
+    const T* qy = q;
+    const T* qx = q + n;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g / W), j = (int)(g % W);
+        T d = T(0);
+        if (i < H - 1) d += qy[g];
+        if (i > 0) d -= qy[g - W];
+        if (j < W - 1) d += qx[g];
+        if (j > 0) d -= qx[g - 1];
+        out[g] = d;
+    }
+}
+
+static int grid1d(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (int)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+template <typename T>
+void launch_grad(tvs_ctx* ctx, int H, int W, const T* u, T* q) {
+    hipLaunchKernelGGL((grad_kernel<T>), dim3(grid1d((size_t)H * W)), dim3(256), 0, ctx->stream,
+                       H, W, u, q);
+    TVS_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T* u) {
+    hipLaunchKernelGGL((div_kernel<T>), dim3(grid1d((size_t)H * W)), dim3(256), 0, ctx->stream,
+                       H, W, q, u);
+    TVS_LAUNCH_CHECK();
+}
+
+#define TVS_INST(T)                                                                          \
+    template T* run_fgp<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, const FgpConfig&); \
+    template void launch_finalize<T>(tvs_ctx*, int, int, const Finalize<T>&);                \
+    template void launch_grad<T>(tvs_ctx*, int, int, const T*, T*);                          \
+    template void launch_div<T>(tvs_ctx*, int, int, const T*, T*);
+TVS_INST(float)
+TVS_INST(double)
+#undef TVS_INST
+
+}  // namespace tvs

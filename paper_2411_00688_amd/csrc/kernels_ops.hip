@@ -1,0 +1,627 @@
+// Forward operators A, their adjoints, and the data-fidelity steps fused into
+// their epilogues, for gfx950.
+//
+//  - identity: pointwise, 32 x 32 tiles.
+//  - periodic blur: LDS tile with a periodic halo (radius <= 8).
+//  - Joseph parallel-beam projector (ray-driven, one wavefront per 64 adjacent
+//    bins of one angle, the row range split over 4 wavefronts and summed in a
+//    fixed order), and its exact transpose as a pixel-driven gather (no
+//    atomics): each pixel finds, per angle, the few rays whose interpolation
+//    touches it and recomputes their weights with the projector's arithmetic.
+//
+// Data-fidelity epilogue (PrimalStep), with s = grad f(x) (ProxSkip) or
+// s = A^T y (PDHGSkip-2) at a pixel:
+//   w = x - step s;  xhat = w + step h
+//   theta = 1: v = w + (step - step/p) h  and xhat are stored for the prox
+//   theta = 0: x <- xhat; for PDHGSkip also xbar = 2 xhat - x_old (and its
+//              transpose, which the projector reads for column-stepping rays).
+#include "tvs_internal.hpp"
+
+namespace tvs {
+
+template <typename T>
+__device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, T s) {
+    const T x = ps.x[g];
+    const T hh = ps.h[g];
+    const T w = x - ps.step * s;
+    const T xh = w + ps.step * hh;
+    if (ps.theta) {
+        ps.v[g] = w + ps.coef * hh;
+        ps.xhat[g] = xh;
+        return T(0);
+    }
+    ps.x[g] = xh;
+    if (ps.pdhg) {
+        const T xb = T(2) * xh - x;
+        ps.xbar[g] = xb;
+        return xb;
+    }
+    return T(0);
+}
+
+// Splits the 32.32 fixed-point coordinate U (an integer-valued double with
+// |U| < 2^51) into floor(U / 2^32) and the fraction, from the bits of
+// U + 1.5 2^52, whose 52-bit mantissa is exactly U + 2^51.
+__device__ __forceinline__ void fx_split(double U, int& j0, float& f) {
+    const double v = U + 6755399441055744.0;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    j0 = (int)((unsigned)(b >> 32) & 0xFFFFFu) - 524288;
+    f = (float)(unsigned)b * 2.3283064365386963e-10f;
+}
+
+static int grid1d(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (int)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+// ------------------------------------------------------------- pointwise
+template <typename T>
+__global__ void axpby_kernel(size_t n, T a, const T* x, T b, const T* y, T* out) {
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x)
+        out[g] = a * x[g] + b * y[g];
+}
+
+template <typename T>
+__global__ void copy_kernel(size_t n, const T* x, T* y) {
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x)
+        y[g] = x[g];
+}
+
+template <typename T>
+__global__ void fill_kernel(size_t n, T val, T* y) {
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x)
+        y[g] = val;
+}
+
+template <typename T>
+void launch_axpby(tvs_ctx* ctx, size_t n, T a, const T* x, T b, const T* y, T* out) {
+    hipLaunchKernelGGL((axpby_kernel<T>), dim3(grid1d(n)), dim3(256), 0, ctx->stream, n, a, x, b,
+                       y, out);
+    TVS_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_copy(tvs_ctx* ctx, size_t n, const T* x, T* y) {
+    hipLaunchKernelGGL((copy_kernel<T>), dim3(grid1d(n)), dim3(256), 0, ctx->stream, n, x, y);
+    TVS_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_fill(tvs_ctx* ctx, size_t n, T val, T* y) {
+    hipLaunchKernelGGL((fill_kernel<T>), dim3(grid1d(n)), dim3(256), 0, ctx->stream, n, val, y);
+    TVS_LAUNCH_CHECK();
+}
+
+// 32 x 32 LDS transpose: xT[j][i] = x[i][j]
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(int H, int W, const T* x, T* xT) {
+    __shared__ T t[32][33];
+    const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / 32, lj = idx % 32;
+        if (i0 + li < H && j0 + lj < W) t[li][lj] = x[(size_t)(i0 + li) * W + j0 + lj];
+    }
+    __syncthreads();
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int jj = idx / 32, ii = idx % 32;
+        if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * H + i0 + ii] = t[ii][jj];
+    }
+}
+
+template <typename T>
+void launch_transpose(tvs_ctx* ctx, int H, int W, const T* x, T* xT) {
+    hipLaunchKernelGGL((transpose_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256), 0,
+                       ctx->stream, H, W, x, xT);
+    TVS_LAUNCH_CHECK();
+}
+
+// Writes the 32 x 32 tile of xbar staged in LDS to xbarT, coalesced.
+template <typename T>
+__device__ __forceinline__ void store_tile_transposed(T (*s_t)[33], int i0, int j0, int H, int W,
+                                                      T* xT) {
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int jj = idx / 32, ii = idx % 32;
+        if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * H + i0 + ii] = s_t[ii][jj];
+    }
+}
+
+// ---------------------------------------------------------------- identity
+// s = x - b (ProxSkip gradient, from_y = 0) or s = y (PDHGSkip A^T y, from_y = 1)
+template <typename T>
+__global__ __launch_bounds__(256) void identity_step_kernel(int H, int W, const T* src,
+                                                            const T* b, PrimalStep<T> ps,
+                                                            int from_y) {
+    __shared__ T s_t[32][33];
+    const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / 32, lj = idx % 32;
+        const int i = i0 + li, j = j0 + lj;
+        if (i < H && j < W) {
+            const size_t g = (size_t)i * W + j;
+            const T s = from_y ? src[g] : ps.x[g] - b[g];
+            s_t[li][lj] = primal_step(ps, g, s);
+        }
+    }
+    if (ps.pdhg && !ps.theta && ps.xbarT) store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT);
+}
+
+template <typename T>
+void launch_identity_step(tvs_ctx* ctx, int H, int W, const T* b, const PrimalStep<T>& ps) {
+    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256),
+                       0, ctx->stream, H, W, (const T*)nullptr, b, ps, 0);
+    TVS_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_identity_adj_step(tvs_ctx* ctx, int H, int W, const T* y, const PrimalStep<T>& ps) {
+    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256),
+                       0, ctx->stream, H, W, y, (const T*)nullptr, ps, 1);
+    TVS_LAUNCH_CHECK();
+}
+
+// y = (y + tau (xbar - b)) / (1 + tau), pointwise (identity PDHGSkip dual step)
+template <typename T>
+__global__ void dual_prox_pointwise_kernel(size_t n, const T* xb, const T* b, T* y, T tau) {
+    const T den = T(1) + tau;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+         g += (size_t)gridDim.x * blockDim.x)
+        y[g] = (y[g] + tau * (xb[g] - b[g])) / den;
+}
+
+template <typename T>
+void launch_dual_prox_pointwise(tvs_ctx* ctx, size_t n, const T* xb, const T* b, T* y, T tau) {
+    hipLaunchKernelGGL((dual_prox_pointwise_kernel<T>), dim3(grid1d(n)), dim3(256), 0,
+                       ctx->stream, n, xb, b, y, tau);
+    TVS_LAUNCH_CHECK();
+}
+
+// -------------------------------------------------------------------- blur
+enum BlurMode { BLUR_STORE = 0, BLUR_RESIDUAL = 1, BLUR_DUAL_PROX = 2, BLUR_PRIMAL = 3 };
+
+template <typename T>
+struct BlurArgs {
+    const T* x;
+    const T* k;
+    int kh, kw;
+    int adjoint;
+    const T* b;
+    T* out;
+    int mode;
+    T tau;
+    PrimalStep<T> ps;
+    int H, W;
+};
+
+// (A x)_{i,j} = sum_{a,c} k[a][c] x[(i - (a - kh/2)) mod H][(j - (c - kw/2)) mod W]
+// (A^T y)_{i,j} = sum_{a,c} k[a][c] y[(i + (a - kh/2)) mod H][(j + (c - kw/2)) mod W]
+template <typename T>
+__global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
+    constexpr int TW = 32, TH = 32, RMAX = 8;
+    constexpr int LW = TW + 2 * RMAX, LH = TH + 2 * RMAX;
+    __shared__ T s_x[LH][LW + 1];
+    __shared__ T s_k[17 * 17];
+    __shared__ T s_t[32][33];
+    const int H = a.H, W = a.W;
+    const int rh = a.kh / 2, rw = a.kw / 2;
+    const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
+    const int tid = (int)threadIdx.x;
+    for (int idx = tid; idx < a.kh * a.kw; idx += 256) s_k[idx] = a.k[idx];
+    const int lh = TH + 2 * rh, lw = TW + 2 * rw;
+    for (int idx = tid; idx < lh * lw; idx += 256) {
+        const int li = idx / lw, lj = idx % lw;
+        int gi = (i0 - rh + li) % H;
+        if (gi < 0) gi += H;
+        int gj = (j0 - rw + lj) % W;
+        if (gj < 0) gj += W;
+        s_x[li][lj] = a.x[(size_t)gi * W + gj];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = tid + p * 256;
+        const int li = idx / TW, lj = idx % TW;
+        const int i = i0 + li, j = j0 + lj;
+        if (i >= H || j >= W) continue;
+        T s = T(0);
+        if (!a.adjoint) {
+            for (int r = 0; r < a.kh; ++r)
+                for (int c = 0; c < a.kw; ++c)
+                    s += s_k[r * a.kw + c] * s_x[li + 2 * rh - r][lj + 2 * rw - c];
+        } else {
+            for (int r = 0; r < a.kh; ++r)
+                for (int c = 0; c < a.kw; ++c) s += s_k[r * a.kw + c] * s_x[li + r][lj + c];
+        }
+        const size_t g = (size_t)i * W + j;
+        if (a.mode == BLUR_STORE) {
+            a.out[g] = s;
+        } else if (a.mode == BLUR_RESIDUAL) {
+            a.out[g] = s - a.b[g];
+        } else if (a.mode == BLUR_DUAL_PROX) {
+            a.out[g] = (a.out[g] + a.tau * (s - a.b[g])) / (T(1) + a.tau);
+        } else {
+            s_t[li][lj] = primal_step(a.ps, g, s);
+        }
+    }
+    if (a.mode == BLUR_PRIMAL && a.ps.pdhg && !a.ps.theta && a.ps.xbarT)
+        store_tile_transposed<T>(s_t, i0, j0, H, W, a.ps.xbarT);
+}
+
+template <typename T>
+static BlurArgs<T> blur_args(const tvs_op* op, bool adjoint) {
+    BlurArgs<T> a{};
+    a.k = sizeof(T) == 4 ? (const T*)op->blur.k_f : (const T*)op->blur.k_d;
+    a.kh = op->blur.kh;
+    a.kw = op->blur.kw;
+    a.adjoint = adjoint ? 1 : 0;
+    a.H = op->H;
+    a.W = op->W;
+    return a;
+}
+
+template <typename T>
+static void launch_blur_args(tvs_ctx* ctx, const BlurArgs<T>& a) {
+    hipLaunchKernelGGL((blur_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)), dim3(256), 0,
+                       ctx->stream, a);
+    TVS_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_blur(tvs_ctx* ctx, const tvs_op* op, bool adjoint, const T* x, const T* b, T* out) {
+    BlurArgs<T> a = blur_args<T>(op, adjoint);
+    a.x = x;
+    a.b = b;
+    a.out = out;
+    a.mode = b ? BLUR_RESIDUAL : BLUR_STORE;
+    launch_blur_args(ctx, a);
+}
+
+template <typename T>
+void launch_blur_dual_prox(tvs_ctx* ctx, const tvs_op* op, const T* xbar, const T* b, T* y, T tau) {
+    BlurArgs<T> a = blur_args<T>(op, false);
+    a.x = xbar;
+    a.b = b;
+    a.out = y;
+    a.mode = BLUR_DUAL_PROX;
+    a.tau = tau;
+    launch_blur_args(ctx, a);
+}
+
+template <typename T>
+void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const PrimalStep<T>& ps) {
+    BlurArgs<T> a = blur_args<T>(op, true);
+    a.x = r;
+    a.mode = BLUR_PRIMAL;
+    a.ps = ps;
+    launch_blur_args(ctx, a);
+}
+
+// ------------------------------------------------------------------ Joseph
+template <typename T>
+struct JFwdArgs {
+    const JAngle* ang;
+    const T* x;    // H x W
+    const T* xT;   // W x H (for column-stepping rays)
+    const T* b;
+    T* y;
+    int H, W, n_det;
+    int epi;
+    T tau;
+};
+
+// Block: 64 adjacent bins of one angle (lane = bin) x SEG wavefronts, each
+// summing a contiguous quarter of the step range; the partial sums are added
+// in a fixed order, so the result is deterministic.
+template <typename T, int SEG>
+__global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
+    __shared__ T part[SEG][64];
+    const JAngle g = a.ang[blockIdx.y];
+    const int lane = (int)threadIdx.x & 63;
+    const int seg = (int)threadIdx.x >> 6;
+    const int d = (int)blockIdx.x * 64 + lane;
+    const int n_step = g.cls ? a.W : a.H;
+    const int n_int = g.cls ? a.H : a.W;
+    const T* img = g.cls ? a.xT : a.x;
+    const int s0 = (seg * n_step) / SEG, s1 = ((seg + 1) * n_step) / SEG;
+    T acc = T(0);
+    if (d < a.n_det) {
+        const double dd = (double)d;
+        int lo = s0, hi = s1;
+        // steps whose sample can touch the image: -1 <= u < n_int, u = A d + B s + C
+        const double base = fma(g.A, dd, g.C);
+        if (g.B != 0.0) {
+            double t1 = (-1.0 - base) / g.B, t2 = ((double)n_int - base) / g.B;
+            double tmin = t1 < t2 ? t1 : t2, tmax = t1 < t2 ? t2 : t1;
+            // clamp both ends into [s0 - 2, s1 + 2] before converting to int
+            const double cl = (double)(s0 - 2), ch = (double)(s1 + 2);
+            tmin = tmin > cl ? (tmin < ch ? tmin : ch) : cl;
+            tmax = tmax < ch ? (tmax > cl ? tmax : cl) : ch;
+            const int a_lo = (int)floor(tmin) - 1, a_hi = (int)ceil(tmax) + 2;
+            lo = a_lo > lo ? a_lo : lo;
+            hi = a_hi < hi ? a_hi : hi;
+        } else {
+            const double u = fma(g.A, dd, fma(g.B, 0.0, g.C));
+            if (!(u >= -1.0 && u < (double)n_int)) hi = lo;
+        }
+        // Unrolled by 4 with clamped indices and masked weights, so that all
+        // eight gathers of a group are in flight together.
+        const int last = n_int - 1;
+        double U = 0.0;
+        if constexpr (sizeof(T) == 4) U = fma(g.Bq, (double)lo, fma(g.Aq, dd, g.Cq));
+        for (int s = lo; s < hi; s += 4) {
+            T v0[4], v1[4], w0[4], w1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int sk = s + k;
+                const bool ok = sk < hi;
+                const int sc = ok ? sk : lo;
+                int j0;
+                T f;
+                if constexpr (sizeof(T) == 4) {
+                    float ff;
+                    fx_split(U, j0, ff);
+                    f = ff;
+                    U += g.Bq;
+                } else {
+                    const double u = fma(g.A, dd, fma(g.B, (double)sc, g.C));
+                    const double fl = floor(u);
+                    f = (T)(u - fl);
+                    j0 = (int)fl;
+                }
+                const int c0 = j0 < 0 ? 0 : (j0 > last ? last : j0);
+                const int c1 = j0 + 1 < 0 ? 0 : (j0 + 1 > last ? last : j0 + 1);
+                w0[k] = (ok && j0 >= 0 && j0 <= last) ? T(1) - f : T(0);
+                w1[k] = (ok && j0 + 1 >= 0 && j0 + 1 <= last) ? f : T(0);
+                const T* row = img + (size_t)sc * n_int;
+                v0[k] = row[c0];
+                v1[k] = row[c1];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc += w0[k] * v0[k];
+                acc += w1[k] * v1[k];
+            }
+        }
+    }
+    part[seg][lane] = acc;
+    __syncthreads();
+    if (seg == 0 && d < a.n_det) {
+        T s = part[0][lane];
+#pragma unroll
+        for (int k = 1; k < SEG; ++k) s += part[k][lane];
+        s *= (T)g.wgt;
+        const size_t o = (size_t)blockIdx.y * a.n_det + d;
+        if (a.epi == FWD_STORE) {
+            a.y[o] = s;
+        } else if (a.epi == FWD_RESIDUAL) {
+            a.y[o] = s - a.b[o];
+        } else {
+            a.y[o] = (a.y[o] + a.tau * (s - a.b[o])) / (T(1) + a.tau);
+        }
+    }
+}
+
+template <typename T>
+void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b, T* y,
+                       int epi, T tau) {
+    JFwdArgs<T> a;
+    a.ang = op->joseph.ang;
+    a.x = x;
+    a.xT = xT;
+    a.b = b;
+    a.y = y;
+    a.H = op->H;
+    a.W = op->W;
+    a.n_det = op->joseph.n_det;
+    a.epi = epi;
+    a.tau = tau;
+    dim3 grid(div_up(a.n_det, 64), op->joseph.n_ang);
+    hipLaunchKernelGGL((joseph_fwd_kernel<T, 4>), grid, dim3(256), 0, ctx->stream, a);
+    TVS_LAUNCH_CHECK();
+}
+
+template <typename T>
+struct JAdjArgs {
+    const JAngle* ang;
+    int n_ang;
+    const T* y;
+    int H, W, n_det;
+    T* x_out;
+    PrimalStep<T> ps;
+    int has_ps;
+};
+
+// One angle of the backprojector for the thread's 4 pixels, with NC
+// candidate rays each: the 4 * NC gathers are issued before any weight is
+// formed (clamped indices, masked weights, no branches around loads).
+template <typename T, int NC>
+__device__ __forceinline__ void bp_angle(const JAngle& g, const T* __restrict__ yrow, int n_det,
+                                         int i_base, int j, T (&acc)[4]) {
+    int d1[4], t[4];
+    double K[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i_base + 8 * r;
+        const int s_idx = g.cls ? j : i;
+        t[r] = g.cls ? i : j;
+        if constexpr (sizeof(T) == 4) {
+            K[r] = fma(g.Bq, (double)s_idx, g.Cq);
+            const float Kf = (float)K[r] * 2.3283064365386963e-10f;
+            d1[r] = (int)floorf(((float)t[r] - Kf) * g.inv_Af - g.half_spanf);
+        } else {
+            K[r] = fma(g.B, (double)s_idx, g.C);
+            d1[r] = (int)floor(((double)t[r] - K[r]) * g.inv_A - g.half_span);
+        }
+    }
+    T yv[4][NC];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int d = d1[r] + c;
+            yv[r][c] = yrow[d < 0 ? 0 : (d >= n_det ? n_det - 1 : d)];
+        }
+    const T wgt = (T)g.wgt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        T sum = T(0);
+        double U = 0.0;
+        if constexpr (sizeof(T) == 4) U = fma(g.Aq, (double)d1[r], K[r]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int d = d1[r] + c;
+            int jj;
+            T f;
+            if constexpr (sizeof(T) == 4) {
+                float ff;
+                fx_split(U, jj, ff);
+                f = ff;
+                U += g.Aq;
+            } else {
+                const double u = fma(g.A, (double)d, K[r]);
+                const double fl = floor(u);
+                f = (T)(u - fl);
+                jj = (int)fl;
+            }
+            T wt = (jj == t[r]) ? (T(1) - f) : ((jj == t[r] - 1) ? f : T(0));
+            wt = (d >= 0 && d < n_det) ? wt : T(0);
+            sum += wt * yv[r][c];
+        }
+        acc[r] += wgt * sum;
+    }
+}
+
+// Pixel-driven transpose of joseph_fwd.  Block: a 32 x 32 pixel tile, 256
+// threads, 4 pixels each (rows li, li + 8, li + 16, li + 24).  For every angle
+// (uniform across the block) each pixel enumerates the n_cand rays around
+// the one whose sample lands on it and accumulates
+//   (1 - f) y[a][d]  if the ray's sample at this step has floor(u) == t
+//   f y[a][d]        if floor(u) == t - 1
+// where t is the pixel's interpolation index and u is recomputed exactly as
+// the projector computes it.
+template <typename T>
+__global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
+    __shared__ T s_t[32][33];
+    const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
+    const int lj = (int)threadIdx.x & 31, lr = (int)threadIdx.x >> 5;  // lr in [0, 8)
+    const int j = j0 + lj;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    const int n_det = a.n_det;
+    for (int an = 0; an < a.n_ang; ++an) {
+        const JAngle g = a.ang[an];
+        const T* yrow = a.y + (size_t)an * n_det;
+        switch (g.n_cand) {
+            case 2: bp_angle<T, 2>(g, yrow, n_det, i0 + lr, j, acc); break;
+            case 3: bp_angle<T, 3>(g, yrow, n_det, i0 + lr, j, acc); break;
+            case 4: bp_angle<T, 4>(g, yrow, n_det, i0 + lr, j, acc); break;
+            default: {
+                const T wgt = (T)g.wgt;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + lr + 8 * r;
+                    const int s_idx = g.cls ? j : i;
+                    const int t_idx = g.cls ? i : j;
+                    T sum = T(0);
+                    if constexpr (sizeof(T) == 4) {
+                        const double K = fma(g.Bq, (double)s_idx, g.Cq);
+                        const float Kf = (float)K * 2.3283064365386963e-10f;
+                        const int d1 = (int)floorf(((float)t_idx - Kf) * g.inv_Af - g.half_spanf);
+                        double U = fma(g.Aq, (double)d1, K);
+                        for (int c = 0; c < g.n_cand; ++c, U += g.Aq) {
+                            const int d = d1 + c;
+                            if (d >= 0 && d < n_det) {
+                                int jj;
+                                float f;
+                                fx_split(U, jj, f);
+                                const T wt = (jj == t_idx) ? (T(1) - f) : ((jj == t_idx - 1) ? f : T(0));
+                                sum += wt * yrow[d];
+                            }
+                        }
+                    } else {
+                        const double K = fma(g.B, (double)s_idx, g.C);
+                        const int d1 = (int)floor(((double)t_idx - K) * g.inv_A - g.half_span);
+                        for (int c = 0; c < g.n_cand; ++c) {
+                            const int d = d1 + c;
+                            if (d >= 0 && d < n_det) {
+                                const double u = fma(g.A, (double)d, K);
+                                const double fl = floor(u);
+                                const T f = (T)(u - fl);
+                                const int jj = (int)fl;
+                                const T wt = (jj == t_idx) ? (T(1) - f) : ((jj == t_idx - 1) ? f : T(0));
+                                sum += wt * yrow[d];
+                            }
+                        }
+                    }
+                    acc[r] += wgt * sum;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int li = lr + 8 * r;
+        const int i = i0 + li;
+        if (i < a.H && j < a.W) {
+            const size_t gidx = (size_t)i * a.W + j;
+            if (a.has_ps)
+                s_t[li][lj] = primal_step(a.ps, gidx, acc[r]);
+            else
+                a.x_out[gidx] = acc[r];
+        }
+    }
+    if (a.has_ps && a.ps.pdhg && !a.ps.theta && a.ps.xbarT) {
+        __syncthreads();
+        for (int p = 0; p < 4; ++p) {
+            const int idx = (int)threadIdx.x + p * 256;
+            const int jj = idx / 32, ii = idx % 32;
+            if (i0 + ii < a.H && j0 + jj < a.W)
+                a.ps.xbarT[(size_t)(j0 + jj) * a.H + i0 + ii] = s_t[ii][jj];
+        }
+    }
+}
+
+template <typename T>
+void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
+                       const PrimalStep<T>* ps) {
+    JAdjArgs<T> a{};
+    a.ang = op->joseph.ang;
+    a.n_ang = op->joseph.n_ang;
+    a.y = y;
+    a.H = op->H;
+    a.W = op->W;
+    a.n_det = op->joseph.n_det;
+    a.x_out = x_out;
+    if (ps) {
+        a.ps = *ps;
+        a.has_ps = 1;
+    }
+    dim3 grid(div_up(a.W, 32), div_up(a.H, 32));
+    hipLaunchKernelGGL((joseph_adj_kernel<T>), grid, dim3(256), 0, ctx->stream, a);
+    TVS_LAUNCH_CHECK();
+}
+
+#define TVS_INST(T)                                                                              \
+    template void launch_axpby<T>(tvs_ctx*, size_t, T, const T*, T, const T*, T*);               \
+    template void launch_copy<T>(tvs_ctx*, size_t, const T*, T*);                                \
+    template void launch_fill<T>(tvs_ctx*, size_t, T, T*);                                       \
+    template void launch_transpose<T>(tvs_ctx*, int, int, const T*, T*);                         \
+    template void launch_identity_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&);   \
+    template void launch_identity_adj_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&); \
+    template void launch_dual_prox_pointwise<T>(tvs_ctx*, size_t, const T*, const T*, T*, T);    \
+    template void launch_blur<T>(tvs_ctx*, const tvs_op*, bool, const T*, const T*, T*);         \
+    template void launch_blur_dual_prox<T>(tvs_ctx*, const tvs_op*, const T*, const T*, T*, T);  \
+    template void launch_blur_adjoint_step<T>(tvs_ctx*, const tvs_op*, const T*, const PrimalStep<T>&); \
+    template void launch_joseph_fwd<T>(tvs_ctx*, const tvs_op*, const T*, const T*, const T*, T*, int, T); \
+    template void launch_joseph_adj<T>(tvs_ctx*, const tvs_op*, const T*, T*, const PrimalStep<T>*);
+TVS_INST(float)
+TVS_INST(double)
+#undef TVS_INST
+
+}  // namespace tvs

@@ -1,0 +1,257 @@
+// Internal declarations of the gfx950 TV-skip library: context, operators,
+// scratch memory and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tvskip.h"
+
+namespace tvs {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+
+struct Error {
+    tvs_status status;
+    std::string msg;
+};
+
+#define TVS_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            throw ::tvs::Error{e_ == hipErrorOutOfMemory ? TVS_ERR_OOM          \
+                                                         : TVS_ERR_DEVICE,     \
+                               std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define TVS_LAUNCH_CHECK() TVS_HIP(hipGetLastError())
+
+#define TVS_REQUIRE(cond, st, msg)                                             \
+    do {                                                                       \
+        if (!(cond)) throw ::tvs::Error{(st), (msg)};                          \
+    } while (0)
+
+// ------------------------------------------------------------------ scratch
+// Grow-only device buffers owned by the context, one per named slot.  A slot
+// is never shrunk, so pointers stay valid until the slot grows.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+enum Slot : int {
+    S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
+    S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_COUNT
+};
+
+struct GraphEntry;
+
+struct FgpConfig {
+    int tile_w = 32, tile_h = 32, steps = 4;
+};
+
+inline uint64_t fgp_key(int H, int W, int dtype_bytes) {
+    return ((uint64_t)(uint32_t)H << 32) | ((uint64_t)(uint32_t)W << 4) | (uint64_t)dtype_bytes;
+}
+
+}  // namespace tvs
+
+struct tvs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    tvs::Scratch slots[tvs::S_COUNT];
+    int n_cu = 0;
+    // FGP momentum table: beta[k] for k < beta_len (float and double copies)
+    int beta_len = 0;
+    // FGP tile / temporal-depth choice per (H, W, dtype), set by the autotuner
+    std::map<uint64_t, tvs::FgpConfig> fgp_tuned;
+    // cached graphs of solver runs
+    std::vector<tvs::GraphEntry*> graphs;
+};
+
+namespace tvs {
+
+void* scratch(tvs_ctx* ctx, Slot s, size_t bytes);
+
+enum OpKind { OP_IDENTITY = 0, OP_BLUR = 1, OP_JOSEPH = 2 };
+
+// Per-angle Joseph geometry.  For a ray (a, d) the sampled step index s runs
+// over image rows (cls 0) or columns (cls 1); the continuous interpolation
+// coordinate at step s is u = A d + B s + C.  The projector and the
+// backprojector evaluate u with exactly the same arithmetic, so the two are
+// exact transposes of each other:
+//  - float64 data: u = fma(A, d, fma(B, s, C)) in float64, floor / fraction;
+//  - float32 data: u in 32.32 fixed point, U = u 2^32 = Aq d + Bq s + Cq with
+//    integer-valued float64 coefficients (Aq = round(A 2^32) ...).  Every
+//    intermediate is an integer below 2^52, so all float64 sums and products
+//    are exact, either kernel may step U incrementally, and floor(u) and the
+//    fraction are read from the bits of U + 1.5 2^52.  Rounding the
+//    coefficients moves a sample by less than 2e-7 pixel.
+struct JAngle {
+    double A, B, C;    // coefficients of u
+    double inv_A;      // 1 / A
+    double half_span;  // 1 / |A|
+    double wgt;        // pixel / max(|cos|, |sin|)
+    double Aq, Bq, Cq; // integer-valued 32.32 fixed-point copies of A, B, C
+    float inv_Af, half_spanf;
+    int cls;           // 0: steps over rows, interpolates columns; 1: the reverse
+    int n_cand;        // candidate rays per pixel in the backprojector
+};
+
+struct JosephGeom {
+    int n_ang = 0, n_det = 0;
+    double pixel = 0, det_spacing = 0;
+    JAngle* ang = nullptr;   // device table
+    std::vector<JAngle> host;
+};
+
+struct BlurGeom {
+    int kh = 0, kw = 0;
+    float* k_f = nullptr;   // device kernel (row-major kh x kw)
+    double* k_d = nullptr;
+};
+
+}  // namespace tvs
+
+struct tvs_op {
+    tvs_ctx* ctx = nullptr;
+    int kind = 0;
+    int H = 0, W = 0;
+    tvs::JosephGeom joseph;
+    tvs::BlurGeom blur;
+    size_t out_size() const {
+        return kind == tvs::OP_JOSEPH ? (size_t)joseph.n_ang * joseph.n_det
+                                      : (size_t)H * W;
+    }
+};
+
+namespace tvs {
+
+// ---------------------------------------------------------------- epilogues
+// What a per-pixel data-fidelity kernel does with s = (grad f) or (A^T y) at
+// a pixel, shared by all operators.
+template <typename T>
+struct PrimalStep {
+    // w = x - step * s;  xhat = w + step * h
+    // theta = 1: v = w + coef * h  (stored), xhat stored
+    // theta = 0: x <- xhat (in place); pdhg: xbar = 2 xhat - x_old (+ transpose)
+    T* x;
+    const T* h;
+    T* xhat;
+    T* v;
+    T* xbar;
+    T* xbarT;
+    T step, coef;
+    int theta;
+    int pdhg;
+};
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on ctx->stream and throw tvs::Error on failure.
+
+// D, div (standalone, unit tests and reductions)
+template <typename T> void launch_grad(tvs_ctx* ctx, int H, int W, const T* u, T* q);
+template <typename T> void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T* u);
+
+// FGP on the dual: runs `iters` iterations from the warm dual in q_inout and
+// returns the buffer holding the final dual (q_inout or a scratch buffer);
+// launch_finalize then forms z and copies the dual back into q_inout.
+FgpConfig fgp_config(tvs_ctx* ctx, int H, int W, int dtype_bytes);
+int fgp_variant_count();
+FgpConfig fgp_variant(int index);
+template <typename T>
+T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
+           T* q_inout, const FgpConfig& cfg);
+
+// z = P_X(v + div q) and the ProxSkip / PDHGSkip bookkeeping after a prox.
+template <typename T>
+struct Finalize {
+    const T* v;
+    const T* q;      // final dual (may differ from q_out)
+    T* q_out;        // caller's dual buffer; written if != q
+    T* z;            // standalone prox output (or nullptr)
+    T* x;            // solver: x_{k+1} = z (old x read first for pdhg)
+    T* h;            // h += rate (z - xhat)
+    const T* xhat;
+    T* xbar;         // pdhg: 2 z - x_old
+    T* xbarT;        // pdhg: transposed copy
+    T rate;
+    int nonneg;
+    int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip
+};
+template <typename T> void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f);
+
+// ProxSkip data step for A = I:  s = x - b, then PrimalStep.
+template <typename T>
+void launch_identity_step(tvs_ctx* ctx, int H, int W, const T* b, const PrimalStep<T>& ps);
+// PDHGSkip data step for A = I:  s = y, then PrimalStep.
+template <typename T>
+void launch_identity_adj_step(tvs_ctx* ctx, int H, int W, const T* y, const PrimalStep<T>& ps);
+// y = (y + tau (xbar - b)) / (1 + tau), pointwise (A = I).
+template <typename T>
+void launch_dual_prox_pointwise(tvs_ctx* ctx, size_t n, const T* xb, const T* b, T* y, T tau);
+// Pointwise: out = x - b (residual for A = I) etc.
+template <typename T>
+void launch_axpby(tvs_ctx* ctx, size_t n, T a, const T* x, T bcoef, const T* y, T* out);
+template <typename T> void launch_copy(tvs_ctx* ctx, size_t n, const T* x, T* y);
+template <typename T> void launch_fill(tvs_ctx* ctx, size_t n, T val, T* y);
+template <typename T> void launch_transpose(tvs_ctx* ctx, int H, int W, const T* x, T* xT);
+
+// Blur: out = A x (- b if b), or A^T y followed by a PrimalStep.
+template <typename T>
+void launch_blur(tvs_ctx* ctx, const tvs_op* op, bool adjoint, const T* x, const T* b, T* out);
+template <typename T>
+void launch_blur_dual_prox(tvs_ctx* ctx, const tvs_op* op, const T* xbar, const T* b, T* y, T tau);
+template <typename T>
+void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const PrimalStep<T>& ps);
+
+// Joseph: forward with epilogue (store, residual, dual prox), adjoint with
+// epilogue (store, primal step).
+enum FwdEpi { FWD_STORE = 0, FWD_RESIDUAL = 1, FWD_DUAL_PROX = 2 };
+template <typename T>
+void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b,
+                       T* y, int epi, T tau);
+template <typename T>
+void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
+                       const PrimalStep<T>* ps);
+
+// Reductions (deterministic two-stage, float64 accumulation).  Each returns
+// a device pointer to one double holding the result.
+template <typename T>
+double* reduce_sq_diff(tvs_ctx* ctx, size_t n, const T* a, const T* b, double* out_dev);
+template <typename T>
+double* reduce_tv(tvs_ctx* ctx, int H, int W, const T* u, double* out_dev);
+template <typename T>
+void reduce_gap(tvs_ctx* ctx, int H, int W, const T* v, const T* z, const T* q, double lam,
+                double* gap_dev, double* primal_dev);
+template <typename T>
+double* reduce_dot(tvs_ctx* ctx, size_t n, const T* a, const T* b, double* out_dev);
+// out[0] = a*x[0] + b*y[0] on the device (scalars combined in float64)
+void launch_combine(tvs_ctx* ctx, const double* x, double a, const double* y, double b, double* out);
+
+// host helpers
+uint64_t splitmix_mix(uint64_t z);
+int coin(uint64_t seed, uint64_t stream, int64_t k, double p);
+const double* beta_table_host(int n);
+
+template <typename T> const T* beta_table_dev(tvs_ctx* ctx, int n);
+
+// graphs (graph.hip)
+// Runs `enqueue` captured into a HIP graph (cached under the call's key) on
+// ctx->stream.  All scratch memory must already be allocated.
+void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void* b,
+               const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue);
+void graph_cache_clear(tvs_ctx* ctx);
+
+inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace tvs

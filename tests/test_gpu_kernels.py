@@ -1,0 +1,272 @@
+"""GPU parity of the library's building blocks against the CPU oracle.
+
+Bars: float64 kernels agree with the oracle to rounding (1e-12 relative, or
+bitwise where both sides do the same single rounding); float32 kernels to
+1e-5 relative L2 (one FGP call) or 1e-6 (one operator application); the
+GPU projector and backprojector are exact transposes of each other (dense
+matrices equal bit for bit); the coin is bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2411_00688_amd as T
+import synth
+from gpu_util import F32, F64, as_input, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(37, 129), (100, 77), (1, 50), (50, 1), (130, 260)]
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------------ D, div
+@pytest.mark.parametrize("H,W", SIZES)
+def test_grad_div(ctx, H, W):
+    r = rng(1)
+    u = r.standard_normal((H, W))
+    q = r.standard_normal((2, H, W))
+    for dt in (F64, F32):
+        ui, qi = as_input(u, dt), as_input(q, dt)
+        gq = torch.empty(2, H, W, dtype=dt, device="cuda")
+        gd = torch.empty(H, W, dtype=dt, device="cuda")
+        T.tvs_grad(ctx, dev(ui, dt), gq)
+        T.tvs_div(ctx, dev(qi, dt), gd)
+        if dt == F64:
+            # one subtraction per entry, same summation order: bitwise
+            assert np.array_equal(host(gq), O.grad(ui))
+            assert np.array_equal(host(gd), O.div(qi))
+        else:
+            assert rel_l2(host(gq), O.grad(ui)) < 1e-7
+            assert rel_l2(host(gd), O.div(qi)) < 1e-7
+
+
+# ------------------------------------------------------------------ FGP
+def warm_dual(r, H, W, lam):
+    q = r.standard_normal((2, H, W)) * lam
+    return O.proj_ball(q, lam)
+
+
+@pytest.mark.parametrize("H,W", SIZES)
+@pytest.mark.parametrize("iters", [1, 2, 3, 9, 50])
+@pytest.mark.parametrize("nonneg", [0, 1])
+def test_fgp_f64(ctx, H, W, iters, nonneg):
+    r = rng(H * 1000 + W + iters)
+    v = r.standard_normal((H, W)) + 0.5
+    lam = 0.3
+    q0 = warm_dual(r, H, W, lam)
+    z_ref, q_ref = O.fgp(v, lam, iters, nonneg=nonneg, q=q0)
+    q = dev(q0, F64)
+    z = torch.empty(H, W, dtype=F64, device="cuda")
+    T.tvs_tv_prox(ctx, dev(v, F64), lam, iters, nonneg, q, z)
+    assert np.max(np.abs(host(z) - z_ref)) < 1e-12 * max(1.0, np.abs(v).max())
+    assert np.max(np.abs(host(q) - q_ref)) < 1e-12
+
+
+@pytest.mark.parametrize("H,W", [(37, 129), (130, 260), (512, 512)])
+def test_fgp_f32(ctx, H, W):
+    r = rng(7)
+    v = as_input(r.standard_normal((H, W)) * 0.3 + 0.5, F32)
+    lam = 0.1
+    z_ref, q_ref = O.fgp(v, lam, 50)
+    q = torch.zeros(2, H, W, dtype=F32, device="cuda")
+    z = torch.empty(H, W, dtype=F32, device="cuda")
+    T.tvs_tv_prox(ctx, dev(v, F32), lam, 50, 0, q, z)
+    assert rel_l2(host(z), z_ref) < 1e-5
+    assert rel_l2(host(q), q_ref) < 1e-4
+
+
+def test_fgp_tile_variants_agree_bitwise(ctx):
+    """Every compiled tile / temporal-depth variant does the same arithmetic per
+    pixel, so all give bit-identical results (a halo or barrier mistake in
+    one of them would not)."""
+    H, W = 203, 151
+    r = rng(8)
+    v = r.standard_normal((H, W))
+    for dt in (F64, F32):
+        outs = []
+        for vi in range(T.tvs_fgp_variant_count()):
+            tw, th, ts = T.tvs_fgp_variant(vi)
+            if dt == F64 and (tw, th, ts) == (64, 32, 8):
+                continue
+            T.tvs_fgp_set_variant(ctx, T.TVS_F64 if dt == F64 else T.TVS_F32, H, W, vi)
+            q = torch.zeros(2, H, W, dtype=dt, device="cuda")
+            z = torch.empty(H, W, dtype=dt, device="cuda")
+            T.tvs_tv_prox(ctx, dev(v, dt), 0.2, 23, 1, q, z)
+            outs.append((host(z), host(q)))
+        T.tvs_fgp_set_variant(ctx, T.TVS_F64 if dt == F64 else T.TVS_F32, H, W, -1)
+        for z, q in outs[1:]:
+            assert np.array_equal(z, outs[0][0]) and np.array_equal(q, outs[0][1])
+
+
+def test_tv_prox_identity_cases_bitwise(ctx):
+    H, W = 70, 90
+    v = rng(9).standard_normal((H, W))
+    for dt in (F64, F32):
+        vi = dev(v, dt)
+        q = torch.zeros(2, H, W, dtype=dt, device="cuda")
+        z = torch.empty_like(vi)
+        T.tvs_tv_prox(ctx, vi, 0.0, 30, 0, q, z)        # lambda = 0: identity
+        assert torch.equal(z, vi) and not torch.any(q != 0)
+        c = torch.full((H, W), 0.37, dtype=dt, device="cuda")
+        q = torch.zeros(2, H, W, dtype=dt, device="cuda")
+        T.tvs_tv_prox(ctx, c, 0.8, 30, 0, q, z)          # constants are fixed points
+        assert torch.equal(z, c)
+
+
+@pytest.mark.parametrize("nonneg", [0, 1])
+def test_gap_parity(ctx, nonneg):
+    H, W = 64, 48
+    r = rng(10)
+    v = r.standard_normal((H, W))
+    lam = 0.25
+    q0 = warm_dual(r, H, W, lam)
+    g_ref, p_ref = O.tv_gap(v, lam, q0, nonneg=nonneg)
+    g, p = T.tvs_tv_gap(ctx, dev(v, F64), lam, nonneg, dev(q0, F64))
+    assert abs(g - g_ref) < 1e-10 * p_ref and abs(p - p_ref) < 1e-12 * p_ref
+    # the relative gap returned by the prox call matches the oracle's
+    z_ref, q_ref = O.fgp(v, lam, 40, nonneg=nonneg, q=q0)
+    g2, p2 = O.tv_gap(v, lam, q_ref, nonneg=nonneg)
+    q = dev(q0, F64)
+    z = torch.empty(H, W, dtype=F64, device="cuda")
+    rel = T.tvs_tv_prox(ctx, dev(v, F64), lam, 40, nonneg, q, z, want_gap=True)
+    assert abs(rel - g2 / p2) < 1e-9 * max(g2 / p2, 1e-12) + 1e-14
+
+
+# --------------------------------------------------------------- operators
+@pytest.mark.parametrize("H,W", [(64, 80), (33, 17)])
+def test_blur_parity(ctx, H, W):
+    r = rng(11)
+    for k in (synth.gaussian_blur_kernel(9, 2.0), r.uniform(-0.2, 1.0, (5, 7))):
+        A = O.blur(H, W, k)
+        x = r.standard_normal((H, W))
+        op = T.tvs_op_blur_periodic(ctx, H, W, k)
+        try:
+            for dt, tol in ((F64, 1e-13), (F32, 1e-6)):
+                xi = as_input(x, dt)
+                y = torch.empty(H, W, dtype=dt, device="cuda")
+                T.tvs_op_apply(op, dev(xi, dt), y)
+                assert rel_l2(host(y), A.apply(xi)) < tol
+                T.tvs_op_adjoint(op, dev(xi, dt), y)
+                assert rel_l2(host(y), A.adjoint(xi)) < tol
+        finally:
+            T.tvs_op_destroy(op)
+
+
+JOSEPH_GEOMS = [
+    # H, W, angles, n_det, pixel, det_spacing
+    (64, 64, synth.parallel_beam_angles(45), 93, 2 / 64, 2 / 64),
+    (37, 50, np.array([0.0, 0.1, 0.7, np.pi / 4, 1.2, np.pi / 2, 2.0, 3 * np.pi / 4, 2.9]),
+     71, 0.05, 0.035),
+    (20, 24, synth.parallel_beam_angles(16), 61, 0.1, 0.03),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(JOSEPH_GEOMS)))
+def test_joseph_parity(ctx, gi):
+    H, W, ang, nd, px, ds = JOSEPH_GEOMS[gi]
+    A = O.joseph(H, W, ang, nd, px, ds)
+    r = rng(12)
+    x = r.standard_normal((H, W))
+    y = r.standard_normal((len(ang), nd))
+    op = T.tvs_op_ct_joseph(ctx, H, W, ang, nd, px, ds)
+    try:
+        for dt, tol in ((F64, 1e-12), (F32, 2e-6)):
+            xi, yi = as_input(x, dt), as_input(y, dt)
+            out = torch.empty(len(ang), nd, dtype=dt, device="cuda")
+            T.tvs_op_apply(op, dev(xi, dt), out)
+            assert rel_l2(host(out), A.apply(xi)) < tol
+            back = torch.empty(H, W, dtype=dt, device="cuda")
+            T.tvs_op_adjoint(op, dev(yi, dt), back)
+            assert rel_l2(host(back), A.adjoint(yi)) < tol
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def _dense_gpu(apply, n_in, in_shape, out_shape, dt):
+    cols = []
+    for c in range(n_in):
+        e = torch.zeros(n_in, dtype=dt, device="cuda")
+        e[c] = 1
+        out = torch.empty(out_shape, dtype=dt, device="cuda")
+        apply(e.view(in_shape), out)
+        cols.append(host(out).ravel())
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("gi", range(len(JOSEPH_GEOMS)))
+def test_joseph_gpu_exact_transpose(ctx, gi):
+    """The backprojector finds every ray that touches a pixel and recomputes
+    the projector's weight with the same arithmetic: the two dense matrices
+    are transposes bit for bit."""
+    H, W, ang, nd, px, ds = JOSEPH_GEOMS[gi]
+    if H * W > 1024:
+        H, W = 16, 20
+    op = T.tvs_op_ct_joseph(ctx, H, W, ang, nd, px, ds)
+    try:
+        for dt in (F64, F32):
+            M = _dense_gpu(lambda a, b: T.tvs_op_apply(op, a, b), H * W, (H, W), (len(ang), nd), dt)
+            MT = _dense_gpu(lambda a, b: T.tvs_op_adjoint(op, a, b), len(ang) * nd,
+                            (len(ang), nd), (H, W), dt)
+            assert np.array_equal(MT, M.T)
+            assert np.count_nonzero(M) > 0
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_joseph_full_size(ctx):
+    """The 512^2, 180-angle, 725-bin CT operator: float32 projector and
+    backprojector against the oracle, and the float64 adjoint identity."""
+    w = synth.WORKLOADS["ct512"]
+    N, na, nd = w.H, w.n_ang, w.n_det
+    ang = synth.parallel_beam_angles(na)
+    A = O.joseph(N, N, ang, nd, w.pixel, w.det_spacing)
+    u, eta = synth.make_inputs(w)
+    op = T.tvs_op_ct_joseph(ctx, N, N, ang, nd, w.pixel, w.det_spacing)
+    try:
+        ui = as_input(u, F32)
+        y = torch.empty(na, nd, dtype=F32, device="cuda")
+        T.tvs_op_apply(op, dev(ui, F32), y)
+        assert rel_l2(host(y), A.apply(ui)) < 2e-6
+        yi = as_input(eta, F32)
+        back = torch.empty(N, N, dtype=F32, device="cuda")
+        T.tvs_op_adjoint(op, dev(yi, F32), back)
+        assert rel_l2(host(back), A.adjoint(yi)) < 2e-6
+        x = torch.tensor(u, device="cuda")
+        yy = torch.tensor(eta, device="cuda")
+        ax = torch.empty(na, nd, dtype=F64, device="cuda")
+        aty = torch.empty(N, N, dtype=F64, device="cuda")
+        T.tvs_op_apply(op, x, ax)
+        T.tvs_op_adjoint(op, yy, aty)
+        lhs = torch.sum(ax * yy).item()
+        rhs = torch.sum(x * aty).item()
+        assert abs(lhs - rhs) < 1e-12 * torch.sum(torch.abs(ax) * torch.abs(yy)).item()
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_op_norm_and_objective(ctx):
+    H = W = 40
+    ang = synth.parallel_beam_angles(30)
+    A = O.joseph(H, W, ang, 59, 2 / H, 2 / H)
+    op = T.tvs_op_ct_joseph(ctx, H, W, ang, 59, 2 / H, 2 / H)
+    try:
+        assert abs(T.tvs_op_norm(op, 300, 7) - A.norm(300, 7)) < 1e-9
+        r = rng(13)
+        x, b = r.standard_normal((H, W)), r.standard_normal((30, 59))
+        for dt, tol in ((F64, 1e-12), (F32, 1e-5)):
+            xi, bi = as_input(x, dt), as_input(b, dt)
+            val = T.tvs_objective(op, dev(bi, dt), dev(xi, dt), 0.05)
+            ref = O.objective(A, bi, xi, 0.05)
+            assert abs(val - ref) < tol * ref
+    finally:
+        T.tvs_op_destroy(op)
+    op = T.tvs_op_identity(ctx, H, W)
+    try:
+        assert abs(T.tvs_op_norm(op, 5, 1) - 1.0) < 1e-14
+    finally:
+        T.tvs_op_destroy(op)
