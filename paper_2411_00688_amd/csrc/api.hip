@@ -49,6 +49,10 @@ void* scratch(tvs_ctx* ctx, Slot s, size_t bytes) {
     size_t want = bytes < 256 ? 256 : bytes;
     want = (want + 255) & ~(size_t)255;
     TVS_HIP(hipMalloc(&sc.ptr, want));
+    // new scratch starts zeroed (the padded projector inputs rely on zero
+    // pads that no kernel writes)
+    TVS_HIP(hipMemset(sc.ptr, 0, want));
+    TVS_HIP(hipDeviceSynchronize());
     sc.bytes = want;
     return sc.ptr;
 }
@@ -273,9 +277,19 @@ extern "C" tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
             e.Aq = std::nearbyint(std::ldexp(e.A, 32));
             e.Bq = std::nearbyint(std::ldexp(e.B, 32));
             e.Cq = std::nearbyint(std::ldexp(e.C, 32));
+            e.Aqi = (long long)e.Aq;
+            e.Bqi = (long long)e.Bq;
+            e.Cqi = (long long)e.Cq;
             e.inv_Af = (float)e.inv_A;
             e.half_spanf = (float)e.half_span;
             g.host[a] = e;
+        }
+        // ray-driven backprojector: rays never share a pixel interval at one
+        // step (|Aq| >= 2^32) and a 60-pixel tile's rays fit the staged window
+        g.rd_ok = true;
+        for (const JAngle& e : g.host) {
+            const double spread = 59.0 * std::fabs(e.B) * e.half_span + 2.0 + 64.0 + 4.0;
+            if (std::fabs(e.Aq) < 4294967296.0 || spread > 127.0) g.rd_ok = false;
         }
         TVS_HIP(hipMalloc(&g.ang, n_ang * sizeof(JAngle)));
         TVS_HIP(hipMemcpy(g.ang, g.host.data(), n_ang * sizeof(JAngle), hipMemcpyHostToDevice));
@@ -310,9 +324,10 @@ static void op_apply(tvs_op* op, const T* x, T* y, const T* b /* nullable: y = A
     } else if (op->kind == OP_BLUR) {
         launch_blur<T>(ctx, op, false, x, b, y);
     } else {
-        T* xT = (T*)scratch(ctx, S_TR_IMG, n * sizeof(T));
-        launch_transpose<T>(ctx, op->H, op->W, x, xT);
-        launch_joseph_fwd<T>(ctx, op, x, xT, b, y, b ? FWD_RESIDUAL : FWD_STORE, T(0));
+        T* xp = (T*)scratch(ctx, S_PADX, (size_t)op->H * (op->W + 2 * JPAD) * sizeof(T)) + JPAD;
+        T* xTp = (T*)scratch(ctx, S_TR_IMG, (size_t)op->W * (op->H + 2 * JPAD) * sizeof(T)) + JPAD;
+        launch_pad_copy<T>(ctx, op->H, op->W, x, xp, xTp);
+        launch_joseph_fwd<T>(ctx, op, xp, xTp, b, y, b ? FWD_RESIDUAL : FWD_STORE, T(0));
     }
 }
 
@@ -573,10 +588,28 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
     T* y = (T*)st->y;
     T* xhat = (T*)scratch(ctx, S_XHAT, n * sizeof(T));
     T* v = (T*)scratch(ctx, S_V, n * sizeof(T));
-    T* xbar = pdhg ? (T*)scratch(ctx, S_XBAR, n * sizeof(T)) : nullptr;
-    T* xbarT = (pdhg && op->kind == OP_JOSEPH) ? (T*)scratch(ctx, S_XBART, n * sizeof(T)) : nullptr;
+    // xbar: the projector reads it through zero-padded copies (row stride
+    // W + 2 JPAD and a transposed copy with row stride H + 2 JPAD)
+    const bool jos = op->kind == OP_JOSEPH;
+    const int xbar_ld = jos ? W + 2 * JPAD : W, xbarT_ld = H + 2 * JPAD;
+    T* xbar = nullptr;
+    T* xbarT = nullptr;
+    if (pdhg && jos) {
+        xbar = (T*)scratch(ctx, S_XBARP, (size_t)H * xbar_ld * sizeof(T)) + JPAD;
+        xbarT = (T*)scratch(ctx, S_XBARTP, (size_t)W * xbarT_ld * sizeof(T)) + JPAD;
+        // zero pads (a fill kernel, so the run stays capturable)
+        launch_fill<T>(ctx, (size_t)H * xbar_ld, T(0), xbar - JPAD);
+        launch_fill<T>(ctx, (size_t)W * xbarT_ld, T(0), xbarT - JPAD);
+    } else if (pdhg) {
+        xbar = (T*)scratch(ctx, S_XBAR, n * sizeof(T));
+    }
     T* res = (T*)scratch(ctx, S_RES, m * sizeof(T));
-    T* xT = (!pdhg && op->kind == OP_JOSEPH) ? (T*)scratch(ctx, S_TR_IMG, n * sizeof(T)) : nullptr;
+    T* xp = nullptr;
+    T* xTp = nullptr;
+    if (!pdhg && jos) {
+        xp = (T*)scratch(ctx, S_PADX, (size_t)H * (W + 2 * JPAD) * sizeof(T)) + JPAD;
+        xTp = (T*)scratch(ctx, S_TR_IMG, (size_t)W * (H + 2 * JPAD) * sizeof(T)) + JPAD;
+    }
     const double step = P->step, p = P->p;
     const double lam = P->alpha * step / p;
     const FgpConfig cfg = fgp_config(ctx, H, W, (int)sizeof(T));
@@ -587,6 +620,8 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
     ps.v = v;
     ps.xbar = xbar;
     ps.xbarT = xbarT;
+    ps.xbar_ld = xbar_ld;
+    ps.xbarT_ld = xbarT_ld;
     ps.step = (T)step;
     ps.coef = (T)(step - step / p);
     ps.pdhg = pdhg ? 1 : 0;
@@ -600,8 +635,8 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
                 launch_blur<T>(ctx, op, false, x, b, res);
                 launch_blur_adjoint_step<T>(ctx, op, res, ps);
             } else {
-                launch_transpose<T>(ctx, H, W, x, xT);
-                launch_joseph_fwd<T>(ctx, op, x, xT, b, res, FWD_RESIDUAL, T(0));
+                launch_pad_copy<T>(ctx, H, W, x, xp, xTp);
+                launch_joseph_fwd<T>(ctx, op, xp, xTp, b, res, FWD_RESIDUAL, T(0));
                 launch_joseph_adj<T>(ctx, op, res, nullptr, &ps);
             }
         } else {
@@ -624,6 +659,8 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
             f.xhat = xhat;
             f.xbar = xbar;
             f.xbarT = xbarT;
+            f.xbar_ld = xbar_ld;
+            f.xbarT_ld = xbarT_ld;
             f.rate = (T)(p / step);
             f.nonneg = P->nonneg;
             f.mode = pdhg ? 2 : 1;
@@ -651,8 +688,14 @@ static void prepare_solver(tvs_op* op, bool pdhg, const tvs_params* P) {
     const size_t n = (size_t)op->H * op->W, m = op->out_size();
     scratch(ctx, S_XHAT, n * sizeof(T));
     scratch(ctx, S_V, n * sizeof(T));
-    if (pdhg) scratch(ctx, S_XBAR, n * sizeof(T));
-    if (op->kind == OP_JOSEPH) scratch(ctx, pdhg ? S_XBART : S_TR_IMG, n * sizeof(T));
+    if (op->kind == OP_JOSEPH) {
+        const size_t rows = (size_t)op->H * (op->W + 2 * JPAD), cols = (size_t)op->W * (op->H + 2 * JPAD);
+        scratch(ctx, pdhg ? S_XBARP : S_PADX, rows * sizeof(T));
+        scratch(ctx, pdhg ? S_XBARTP : S_TR_IMG, cols * sizeof(T));
+        if (sizeof(T) == 4 && op->joseph.rd_ok)
+            scratch(ctx, S_PARTIMG, (size_t)joseph_rd_groups(ctx, op) * n * sizeof(T));
+    }
+    if (pdhg && op->kind != OP_JOSEPH) scratch(ctx, S_XBAR, n * sizeof(T));
     scratch(ctx, S_RES, m * sizeof(T));
     scratch(ctx, S_Q1, 2 * n * sizeof(T));
     scratch(ctx, S_Q2, 2 * n * sizeof(T));

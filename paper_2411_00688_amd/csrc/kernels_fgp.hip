@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
             if (f.mode == 2) {
                 const T xo = f.x[g];
                 const T xb = T(2) * z - xo;
-                f.xbar[g] = xb;
+                f.xbar[(size_t)i * f.xbar_ld + j] = xb;
                 s_t[li][lj] = xb;
             }
             f.x[g] = z;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
             const int idx = (int)threadIdx.x + p * 256;
             const int jj = idx / TH, ii = idx % TH;
             const int i = i0 + ii, j = j0 + jj;
-            if (i < H && j < W) f.xbarT[(size_t)j * H + i] = s_t[ii][jj];
+            if (i < H && j < W) f.xbarT[(size_t)j * f.xbarT_ld + i] = s_t[ii][jj];
         }
     }
 }

@@ -20,7 +20,7 @@
 namespace tvs {
 
 template <typename T>
-__device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, T s) {
+__device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, int i, int j, T s) {
     const T x = ps.x[g];
     const T hh = ps.h[g];
     const T w = x - ps.step * s;
@@ -33,7 +33,7 @@ __device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, T s)
     ps.x[g] = xh;
     if (ps.pdhg) {
         const T xb = T(2) * xh - x;
-        ps.xbar[g] = xb;
+        ps.xbar[(size_t)i * ps.xbar_ld + j] = xb;
         return xb;
     }
     return T(0);
@@ -121,13 +121,13 @@ void launch_transpose(tvs_ctx* ctx, int H, int W, const T* x, T* xT) {
 // Writes the 32 x 32 tile of xbar staged in LDS to xbarT, coalesced.
 template <typename T>
 __device__ __forceinline__ void store_tile_transposed(T (*s_t)[33], int i0, int j0, int H, int W,
-                                                      T* xT) {
+                                                      T* xT, int ldT) {
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int idx = (int)threadIdx.x + p * 256;
         const int jj = idx / 32, ii = idx % 32;
-        if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * H + i0 + ii] = s_t[ii][jj];
+        if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * ldT + i0 + ii] = s_t[ii][jj];
     }
 }
 
@@ -147,10 +147,11 @@ __global__ __launch_bounds__(256) void identity_step_kernel(int H, int W, const 
         if (i < H && j < W) {
             const size_t g = (size_t)i * W + j;
             const T s = from_y ? src[g] : ps.x[g] - b[g];
-            s_t[li][lj] = primal_step(ps, g, s);
+            s_t[li][lj] = primal_step(ps, g, i, j, s);
         }
     }
-    if (ps.pdhg && !ps.theta && ps.xbarT) store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT);
+    if (ps.pdhg && !ps.theta && ps.xbarT)
+        store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
 }
 
 template <typename T>
@@ -247,11 +248,11 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
         } else if (a.mode == BLUR_DUAL_PROX) {
             a.out[g] = (a.out[g] + a.tau * (s - a.b[g])) / (T(1) + a.tau);
         } else {
-            s_t[li][lj] = primal_step(a.ps, g, s);
+            s_t[li][lj] = primal_step(a.ps, g, i, j, s);
         }
     }
     if (a.mode == BLUR_PRIMAL && a.ps.pdhg && !a.ps.theta && a.ps.xbarT)
-        store_tile_transposed<T>(s_t, i0, j0, H, W, a.ps.xbarT);
+        store_tile_transposed<T>(s_t, i0, j0, H, W, a.ps.xbarT, a.ps.xbarT_ld);
 }
 
 template <typename T>
@@ -307,8 +308,9 @@ void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const 
 template <typename T>
 struct JFwdArgs {
     const JAngle* ang;
-    const T* x;    // H x W
-    const T* xT;   // W x H (for column-stepping rays)
+    const T* x;    // element (0, 0) of the padded row-major image
+    const T* xT;   // element (0, 0) of the padded transposed image
+    int x_ld, xT_ld;
     const T* b;
     T* y;
     int H, W, n_det;
@@ -317,8 +319,10 @@ struct JFwdArgs {
 };
 
 // Block: 64 adjacent bins of one angle (lane = bin) x SEG wavefronts, each
-// summing a contiguous quarter of the step range; the partial sums are added
-// in a fixed order, so the result is deterministic.
+// summing a contiguous part of the step range; the partial sums are added in
+// a fixed order, so the result is deterministic.  Each ray visits only the
+// steps whose sample can touch the image (plus at most one step of slack at
+// each end, whose samples read the zero pads and add exact zeros).
 template <typename T, int SEG>
 __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
     __shared__ T part[SEG][64];
@@ -329,6 +333,7 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
     const int n_step = g.cls ? a.W : a.H;
     const int n_int = g.cls ? a.H : a.W;
     const T* img = g.cls ? a.xT : a.x;
+    const int ld = g.cls ? a.xT_ld : a.x_ld;
     const int s0 = (seg * n_step) / SEG, s1 = ((seg + 1) * n_step) / SEG;
     T acc = T(0);
     if (d < a.n_det) {
@@ -339,54 +344,43 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
         if (g.B != 0.0) {
             double t1 = (-1.0 - base) / g.B, t2 = ((double)n_int - base) / g.B;
             double tmin = t1 < t2 ? t1 : t2, tmax = t1 < t2 ? t2 : t1;
-            // clamp both ends into [s0 - 2, s1 + 2] before converting to int
-            const double cl = (double)(s0 - 2), ch = (double)(s1 + 2);
+            // clamp both ends into [s0 - 1, s1 + 1] before converting to int
+            const double cl = (double)(s0 - 1), ch = (double)(s1 + 1);
             tmin = tmin > cl ? (tmin < ch ? tmin : ch) : cl;
             tmax = tmax < ch ? (tmax > cl ? tmax : cl) : ch;
-            const int a_lo = (int)floor(tmin) - 1, a_hi = (int)ceil(tmax) + 2;
+            const int a_lo = (int)floor(tmin), a_hi = (int)ceil(tmax) + 1;
             lo = a_lo > lo ? a_lo : lo;
             hi = a_hi < hi ? a_hi : hi;
         } else {
             const double u = fma(g.A, dd, fma(g.B, 0.0, g.C));
             if (!(u >= -1.0 && u < (double)n_int)) hi = lo;
         }
-        // Unrolled by 4 with clamped indices and masked weights, so that all
-        // eight gathers of a group are in flight together.
-        const int last = n_int - 1;
-        double U = 0.0;
-        if constexpr (sizeof(T) == 4) U = fma(g.Bq, (double)lo, fma(g.Aq, dd, g.Cq));
-        for (int s = lo; s < hi; s += 4) {
-            T v0[4], v1[4], w0[4], w1[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int sk = s + k;
-                const bool ok = sk < hi;
-                const int sc = ok ? sk : lo;
-                int j0;
-                T f;
-                if constexpr (sizeof(T) == 4) {
-                    float ff;
-                    fx_split(U, j0, ff);
-                    f = ff;
-                    U += g.Bq;
-                } else {
-                    const double u = fma(g.A, dd, fma(g.B, (double)sc, g.C));
-                    const double fl = floor(u);
-                    f = (T)(u - fl);
-                    j0 = (int)fl;
-                }
-                const int c0 = j0 < 0 ? 0 : (j0 > last ? last : j0);
-                const int c1 = j0 + 1 < 0 ? 0 : (j0 + 1 > last ? last : j0 + 1);
-                w0[k] = (ok && j0 >= 0 && j0 <= last) ? T(1) - f : T(0);
-                w1[k] = (ok && j0 + 1 >= 0 && j0 + 1 <= last) ? f : T(0);
-                const T* row = img + (size_t)sc * n_int;
-                v0[k] = row[c0];
-                v1[k] = row[c1];
+        const T* row = img + (size_t)(lo > 0 ? lo : 0) * ld;
+        if constexpr (sizeof(T) == 4) {
+            // 32.32 fixed point: U = Aq d + Bq s + Cq exactly, floor(u) is the
+            // high word and the fraction the low word.
+            long long U = g.Aqi * (long long)d + g.Cqi + g.Bqi * (long long)lo;
+#pragma unroll 4
+            for (int s = lo; s < hi; ++s) {
+                const int j0 = (int)(U >> 32);
+                const T f = (T)(unsigned)U * 2.3283064365386963e-10f;
+                const T v0 = row[j0], v1 = row[j0 + 1];
+                acc += (T(1) - f) * v0;
+                acc += f * v1;
+                U += g.Bqi;
+                row += ld;
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                acc += w0[k] * v0[k];
-                acc += w1[k] * v1[k];
+        } else {
+#pragma unroll 4
+            for (int s = lo; s < hi; ++s) {
+                const double u = fma(g.A, dd, fma(g.B, (double)s, g.C));
+                const double fl = floor(u);
+                const T f = (T)(u - fl);
+                const int j0 = (int)fl;
+                const T v0 = row[j0], v1 = row[j0 + 1];
+                acc += (T(1) - f) * v0;
+                acc += f * v1;
+                row += ld;
             }
         }
     }
@@ -415,6 +409,8 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.ang = op->joseph.ang;
     a.x = x;
     a.xT = xT;
+    a.x_ld = op->W + 2 * JPAD;
+    a.xT_ld = op->H + 2 * JPAD;
     a.b = b;
     a.y = y;
     a.H = op->H;
@@ -424,6 +420,60 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.tau = tau;
     dim3 grid(div_up(a.n_det, 64), op->joseph.n_ang);
     hipLaunchKernelGGL((joseph_fwd_kernel<T, 4>), grid, dim3(256), 0, ctx->stream, a);
+    TVS_LAUNCH_CHECK();
+}
+
+// Both zero-padded copies of x (row-major and transposed), pads included.
+// 32 x 32 tiles through LDS; the pad columns are written by the edge tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void pad_copy_kernel(int H, int W, const T* x, T* xp, T* xTp) {
+    __shared__ T t[32][33];
+    const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
+    const int ld = W + 2 * JPAD, ldT = H + 2 * JPAD;
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / 32, lj = idx % 32;
+        const int i = i0 + li, j = j0 + lj;
+        if (i < H && j < W) {
+            const T v = x[(size_t)i * W + j];
+            t[li][lj] = v;
+            xp[(size_t)i * ld + j] = v;
+        }
+    }
+    // pads of the row-major copy: columns -JPAD..-1 and W..W+JPAD-1 of rows i
+    if (blockIdx.x == 0) {
+        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += 256) {
+            const int li = idx / (2 * JPAD), k = idx % (2 * JPAD);
+            const int i = i0 + li;
+            if (i < H) {
+                const int col = k < JPAD ? k - JPAD : W + (k - JPAD);
+                xp[(size_t)i * ld + col] = T(0);
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int jj = idx / 32, ii = idx % 32;
+        if (i0 + ii < H && j0 + jj < W) xTp[(size_t)(j0 + jj) * ldT + i0 + ii] = t[ii][jj];
+    }
+    // pads of the transposed copy: columns -JPAD..-1 and H..H+JPAD-1 of rows j
+    if (blockIdx.y == 0) {
+        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += 256) {
+            const int lj = idx / (2 * JPAD), k = idx % (2 * JPAD);
+            const int j = j0 + lj;
+            if (j < W) {
+                const int col = k < JPAD ? k - JPAD : H + (k - JPAD);
+                xTp[(size_t)j * ldT + col] = T(0);
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_pad_copy(tvs_ctx* ctx, int H, int W, const T* x, T* xp, T* xTp) {
+    hipLaunchKernelGGL((pad_copy_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256), 0,
+                       ctx->stream, H, W, x, xp, xTp);
     TVS_LAUNCH_CHECK();
 }
 
@@ -571,7 +621,7 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
         if (i < a.H && j < a.W) {
             const size_t gidx = (size_t)i * a.W + j;
             if (a.has_ps)
-                s_t[li][lj] = primal_step(a.ps, gidx, acc[r]);
+                s_t[li][lj] = primal_step(a.ps, gidx, i, j, acc[r]);
             else
                 a.x_out[gidx] = acc[r];
         }
@@ -582,9 +632,172 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
             const int idx = (int)threadIdx.x + p * 256;
             const int jj = idx / 32, ii = idx % 32;
             if (i0 + ii < a.H && j0 + jj < a.W)
-                a.ps.xbarT[(size_t)(j0 + jj) * a.H + i0 + ii] = s_t[ii][jj];
+                a.ps.xbarT[(size_t)(j0 + jj) * a.ps.xbarT_ld + i0 + ii] = s_t[ii][jj];
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Ray-driven backprojector for float32 data and detector spacing >= pixel
+// (|A| >= 1, so two rays never sample the same pixel interval at one step).
+//
+// Block: a 60 x 60 pixel tile and one group of angles (angles g, g + G, ...);
+// 4 wavefronts, each owning 15 rows (row-stepping angles) and 15 columns
+// (column-stepping angles) of the tile.  For one angle and one row s, the 64
+// lanes take 64 consecutive rays, compute each ray's sample at that row with
+// the projector's exact fixed-point arithmetic, and scatter its two weights
+// into a per-wavefront LDS line of the 60 pixels (distinct rays land on
+// distinct pixels, so no atomics); each pixel lane then reads its total.  The
+// sinogram window of every angle of the group is staged into LDS once per
+// block.  Each block writes its group's partial image; joseph_adj_sum adds the
+// G partials in a fixed order and applies the epilogue, so the result is
+// deterministic.
+static constexpr int RD_P = 60;     // tile side
+static constexpr int RD_L = 15;     // rows / columns per wavefront
+static constexpr int RD_NB = 128;   // staged bins per angle
+static constexpr int RD_MAXA = 16;  // angles per group
+
+template <typename T>
+struct JAdjRdArgs {
+    const JAngle* ang;
+    int n_ang, groups;
+    const T* y;
+    int H, W, n_det;
+    T* part;  // [groups][H][W]
+};
+
+// first bin of the staged window of angle g for the tile at (i0, j0)
+__device__ __forceinline__ int rd_window(const JAngle& g, int i0, int j0) {
+    const int s0 = g.cls ? j0 : i0, t0 = g.cls ? i0 : j0;
+    const double Ka = fma(g.B, (double)s0, g.C), Kb = fma(g.B, (double)(s0 + RD_P - 1), g.C);
+    const double lo = (double)(t0 - 1), hi = (double)(t0 + RD_P);
+    const double e1 = (lo - Ka) * g.inv_A, e2 = (hi - Ka) * g.inv_A;
+    const double e3 = (lo - Kb) * g.inv_A, e4 = (hi - Kb) * g.inv_A;
+    return (int)floor(fmin(fmin(e1, e2), fmin(e3, e4))) - 3;
+}
+
+// One angle for the wavefront's RD_L steps s_first .. s_first + RD_L - 1 and
+// the tile's pixels t0 .. t0 + RD_P - 1 along the interpolation axis.  The
+// LDS line has 64 float2 slots: slot 2 + p is pixel p; slots 0, 1 and 62, 63
+// absorb samples outside the tile (clamped there), so every lane writes
+// unconditionally.  .x collects (1 - f) y of the ray whose sample floors to
+// the pixel, .y collects f y of the ray that floors to the pixel before.
+__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, int ws, int s_first,
+                                         int t0, int n_step, int lane, float2* ln,
+                                         float (&acc)[RD_L]) {
+    const float wgt = (float)gg.wgt;
+    double K = fma(gg.Bq, (double)s_first, gg.Cq);
+    const double Kr0 = fma(gg.B, (double)s_first, gg.C);
+    double e = fmin(((double)(t0 - 1) - Kr0) * gg.inv_A, ((double)(t0 + RD_P) - Kr0) * gg.inv_A);
+    const double de = -gg.B * gg.inv_A;
+    const double AqL = gg.Aq * (double)lane;
+#pragma unroll
+    for (int r = 0; r < RD_L; ++r) {
+        if (s_first + r < n_step) {
+            const int dfirst = (int)floor(e) - 1;
+            int bi = dfirst - ws + lane;
+            bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
+            const float val = wgt * ys[bi];
+            int jj;
+            float f;
+            fx_split(fma(gg.Aq, (double)dfirst, K) + AqL, jj, f);
+            int lt = jj - t0;
+            lt = lt < -2 ? -2 : (lt > RD_P ? RD_P : lt);
+            ln[lane] = make_float2(0.0f, 0.0f);
+            __asm__ __volatile__("" ::: "memory");
+            ln[lt + 2].x = (1.0f - f) * val;
+            ln[lt + 3].y = f * val;
+            __asm__ __volatile__("" ::: "memory");
+            if (lane < RD_P) {
+                const float2 v = ln[lane + 2];
+                acc[r] += v.x + v.y;
+            }
+            __asm__ __volatile__("" ::: "memory");
+        }
+        K += gg.Bq;
+        e += de;
+    }
+}
+
+__global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
+    __shared__ float yS[RD_MAXA][RD_NB];
+    __shared__ int wst[RD_MAXA];
+    __shared__ float2 line[4][64];
+    __shared__ float tileT[RD_P][RD_P + 1];
+    const int G = a.groups, g = (int)blockIdx.y;
+    const int tiles_x = div_up(a.W, RD_P);
+    const int i0 = ((int)blockIdx.x / tiles_x) * RD_P, j0 = ((int)blockIdx.x % tiles_x) * RD_P;
+    const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int na_g = (a.n_ang - g + G - 1) / G;
+    for (int m = tid; m < na_g; m += 256) wst[m] = rd_window(a.ang[g + m * G], i0, j0);
+    __syncthreads();
+    for (int idx = tid; idx < na_g * RD_NB; idx += 256) {
+        const int m = idx / RD_NB, bb = idx - m * RD_NB;
+        const int d = wst[m] + bb;
+        yS[m][bb] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
+    }
+    __syncthreads();
+    float accR[RD_L], accC[RD_L];
+#pragma unroll
+    for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
+    for (int m = 0; m < na_g; ++m) {
+        const JAngle gg = a.ang[g + m * G];
+        if (gg.cls == 0)
+            rd_angle(gg, yS[m], wst[m], i0 + RD_L * w, j0, a.H, lane, line[w], accR);
+        else
+            rd_angle(gg, yS[m], wst[m], j0 + RD_L * w, i0, a.W, lane, line[w], accC);
+    }
+    // column-stepping sums are held per (row = lane, column = 15 w + c): transpose
+    if (lane < RD_P) {
+#pragma unroll
+        for (int c = 0; c < RD_L; ++c) tileT[lane][RD_L * w + c] = accC[c];
+    }
+    __syncthreads();
+    const size_t plane = (size_t)a.H * a.W;
+#pragma unroll
+    for (int r = 0; r < RD_L; ++r) {
+        const int i = i0 + RD_L * w + r, j = j0 + lane;
+        if (lane < RD_P && i < a.H && j < a.W)
+            a.part[(size_t)g * plane + (size_t)i * a.W + j] = accR[r] + tileT[RD_L * w + r][lane];
+    }
+}
+
+// Sums the G partial images in order and applies the backprojector epilogue
+// (store, or the data step with the transposed xbar copy).  32 x 32 tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void joseph_adj_sum_kernel(const T* part, int G, int H, int W,
+                                                             T* x_out, PrimalStep<T> ps, int has_ps) {
+    __shared__ T s_t[32][33];
+    const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
+    const size_t plane = (size_t)H * W;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / 32, lj = idx % 32;
+        const int i = i0 + li, j = j0 + lj;
+        if (i < H && j < W) {
+            const size_t gi = (size_t)i * W + j;
+            T s = part[gi];
+            for (int k = 1; k < G; ++k) s += part[(size_t)k * plane + gi];
+            if (has_ps)
+                s_t[li][lj] = primal_step(ps, gi, i, j, s);
+            else
+                x_out[gi] = s;
+        }
+    }
+    if (has_ps && ps.pdhg && !ps.theta && ps.xbarT)
+        store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
+}
+
+// Angle groups of the ray-driven backprojector: enough blocks for two per
+// compute unit, at most RD_MAXA angles per group.
+int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op) {
+    const int tiles = div_up(op->W, RD_P) * div_up(op->H, RD_P);
+    int G = div_up(op->joseph.n_ang, RD_MAXA);
+    const int want = div_up(2 * (ctx->n_cu > 0 ? ctx->n_cu : 256), tiles);
+    if (G < want) G = want;
+    if (G > op->joseph.n_ang) G = op->joseph.n_ang;
+    return G;
 }
 
 template <typename T>
@@ -601,6 +814,30 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     if (ps) {
         a.ps = *ps;
         a.has_ps = 1;
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (op->joseph.rd_ok) {
+            const int tiles = div_up(a.W, RD_P) * div_up(a.H, RD_P);
+            const int G = joseph_rd_groups(ctx, op);
+            const size_t plane = (size_t)a.H * a.W;
+            T* part = (T*)scratch(ctx, S_PARTIMG, (size_t)G * plane * sizeof(T));
+            JAdjRdArgs<float> r;
+            r.ang = a.ang;
+            r.n_ang = a.n_ang;
+            r.groups = G;
+            r.y = y;
+            r.H = a.H;
+            r.W = a.W;
+            r.n_det = a.n_det;
+            r.part = part;
+            hipLaunchKernelGGL(joseph_adj_rd_kernel, dim3(tiles, G), dim3(256), 0, ctx->stream, r);
+            TVS_LAUNCH_CHECK();
+            hipLaunchKernelGGL((joseph_adj_sum_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)),
+                               dim3(256), 0, ctx->stream, (const T*)part, G, a.H, a.W, x_out, a.ps,
+                               a.has_ps);
+            TVS_LAUNCH_CHECK();
+            return;
+        }
     }
     dim3 grid(div_up(a.W, 32), div_up(a.H, 32));
     hipLaunchKernelGGL((joseph_adj_kernel<T>), grid, dim3(256), 0, ctx->stream, a);
@@ -619,6 +856,7 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     template void launch_blur_dual_prox<T>(tvs_ctx*, const tvs_op*, const T*, const T*, T*, T);  \
     template void launch_blur_adjoint_step<T>(tvs_ctx*, const tvs_op*, const T*, const PrimalStep<T>&); \
     template void launch_joseph_fwd<T>(tvs_ctx*, const tvs_op*, const T*, const T*, const T*, T*, int, T); \
+    template void launch_pad_copy<T>(tvs_ctx*, int, int, const T*, T*, T*);                      \
     template void launch_joseph_adj<T>(tvs_ctx*, const tvs_op*, const T*, T*, const PrimalStep<T>*);
 TVS_INST(float)
 TVS_INST(double)

@@ -50,7 +50,8 @@ struct Scratch {
 
 enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
-    S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_COUNT
+    S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
+    S_PADX, S_COUNT
 };
 
 struct GraphEntry;
@@ -102,6 +103,7 @@ struct JAngle {
     double half_span;  // 1 / |A|
     double wgt;        // pixel / max(|cos|, |sin|)
     double Aq, Bq, Cq; // integer-valued 32.32 fixed-point copies of A, B, C
+    long long Aqi, Bqi, Cqi;  // the same integers as int64
     float inv_Af, half_spanf;
     int cls;           // 0: steps over rows, interpolates columns; 1: the reverse
     int n_cand;        // candidate rays per pixel in the backprojector
@@ -112,6 +114,9 @@ struct JosephGeom {
     double pixel = 0, det_spacing = 0;
     JAngle* ang = nullptr;   // device table
     std::vector<JAngle> host;
+    // the ray-driven float32 backprojector applies (|A| >= 1 and the staged
+    // sinogram window of a 60-pixel tile fits 128 bins for every angle)
+    bool rd_ok = false;
 };
 
 struct BlurGeom {
@@ -148,8 +153,9 @@ struct PrimalStep {
     const T* h;
     T* xhat;
     T* v;
-    T* xbar;
-    T* xbarT;
+    T* xbar;       // element (0, 0) of xbar, row stride xbar_ld
+    T* xbarT;      // element (0, 0) of the transposed xbar, row stride xbarT_ld
+    int xbar_ld, xbarT_ld;
     T step, coef;
     int theta;
     int pdhg;
@@ -182,8 +188,9 @@ struct Finalize {
     T* x;            // solver: x_{k+1} = z (old x read first for pdhg)
     T* h;            // h += rate (z - xhat)
     const T* xhat;
-    T* xbar;         // pdhg: 2 z - x_old
-    T* xbarT;        // pdhg: transposed copy
+    T* xbar;         // pdhg: 2 z - x_old (row stride xbar_ld)
+    T* xbarT;        // pdhg: transposed copy (row stride xbarT_ld)
+    int xbar_ld, xbarT_ld;
     T rate;
     int nonneg;
     int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip
@@ -215,11 +222,20 @@ template <typename T>
 void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const PrimalStep<T>& ps);
 
 // Joseph: forward with epilogue (store, residual, dual prox), adjoint with
-// epilogue (store, primal step).
+// epilogue (store, primal step).  The projector reads the image through two
+// zero-padded copies, row-major (row stride W + 2 JPAD) and transposed (row
+// stride H + 2 JPAD), each with JPAD zero columns on both sides of every row,
+// so that samples falling just outside the image read zeros instead of
+// being masked; x and xT point at element (0, 0) of each copy.
+constexpr int JPAD = 4;
 enum FwdEpi { FWD_STORE = 0, FWD_RESIDUAL = 1, FWD_DUAL_PROX = 2 };
 template <typename T>
 void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b,
                        T* y, int epi, T tau);
+// Writes both padded copies of the H x W image x (pads included).
+template <typename T>
+void launch_pad_copy(tvs_ctx* ctx, int H, int W, const T* x, T* xp, T* xTp);
+int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op);
 template <typename T>
 void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
                        const PrimalStep<T>* ps);
@@ -252,6 +268,6 @@ void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void*
                const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue);
 void graph_cache_clear(tvs_ctx* ctx);
 
-inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace tvs
