@@ -228,6 +228,44 @@ tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
                         const tvs_params* params, double* obj_trace,
                         uint8_t* theta_trace, tvs_report* report);
 
+/* ---------------------------------------------------------- batched form
+ * Many independent ProxSkip TV-denoising problems (A = I, Sec. 2; the
+ * batched workload of the build) of uneven sizes, solved together: each
+ * outer iteration is one data-step launch over every slice, FGP launches over
+ * the slices whose coin came up (work lists built on the host from the
+ * counter-based coin), and one finalize launch; with TVS_FLAG_GRAPH the whole
+ * run is one HIP graph.  Each slice gets the same arithmetic as tvs_proxskip
+ * with tvs_op_identity and that slice's alpha, p, seed and stream.
+ *
+ * Pools (device, dtype elements): slice s occupies [offset, offset + H*W) of
+ * b_pool, x_pool and h_pool (row-major H x W) and [2 offset, 2 offset +
+ * 2 H W) of q_pool (two planes y, x).  Slices must not overlap.  x, h, q are
+ * in/out.  n_prox_out (nullable, host, n_slices int64): prox calls per slice. */
+typedef struct tvs_slice {
+    int32_t H, W;
+    int64_t offset;      /* element offset of the slice in the pools */
+    double alpha, p;     /* TV weight and prox probability of the slice */
+    uint64_t seed, stream_id;
+} tvs_slice;
+
+typedef struct tvs_batch_params {
+    double step;         /* gamma (1 = 1/L for A = I) */
+    int64_t outer_iters;
+    int32_t inner_iters;
+    int32_t nonneg;
+    int64_t k0;          /* first coin index */
+    int32_t flags;       /* TVS_FLAG_GRAPH */
+    int32_t fgp_variant; /* FGP tile variant index, -1: the context's choice */
+} tvs_batch_params;
+
+tvs_status tvs_proxskip_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
+                                const tvs_slice* slices, const void* b_pool, void* x_pool,
+                                void* h_pool, void* q_pool, const tvs_batch_params* params,
+                                int64_t* n_prox_out);
+/* FGP tile variant used by tvs_proxskip_batched for batches of n_slices
+ * slices in this context (-1 restores the default). */
+tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices, int index);
+
 #ifdef __cplusplus
 }
 #endif

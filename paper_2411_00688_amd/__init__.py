@@ -12,8 +12,8 @@ from __future__ import annotations
 
 import ctypes as C
 
-from ._lib import (TVS_F32, TVS_F64, TVS_FLAG_GRAPH, TvsError, check, lib, tvs_params,
-                   tvs_report, tvs_state)
+from ._lib import (TVS_F32, TVS_F64, TVS_FLAG_GRAPH, TvsError, check, lib, tvs_batch_params,
+                   tvs_params, tvs_report, tvs_slice, tvs_state)
 
 __all__ = [
     "TVS_F32", "TVS_F64", "TVS_FLAG_GRAPH", "TvsError",
@@ -23,6 +23,7 @@ __all__ = [
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
+    "tvs_proxskip_batched", "tvs_fgp_set_variant_batched",
 ]
 
 
@@ -251,3 +252,36 @@ def tvs_fgp_autotune(ctx: int, dtype: int, H: int, W: int, inner_iters: int = 50
     check(lib().tvs_fgp_autotune(C.c_void_p(ctx), int(dtype), int(H), int(W), int(inner_iters),
                                  int(reps), C.byref(best), ms.ctypes.data_as(C.POINTER(C.c_double))))
     return best.value, ms.tolist()
+
+
+# ------------------------------------------------------------ batched form
+def tvs_proxskip_batched(ctx: int, slices, b_pool, x_pool, h_pool, q_pool, step, outer_iters,
+                         inner_iters, nonneg=0, k0=0, graph=False, fgp_variant=-1):
+    """Batched ProxSkip (A = I) in place on the pools.  `slices`: sequence of
+    dicts with H, W, offset, alpha, p, seed, stream_id.  Returns the prox
+    count per slice (numpy int64)."""
+    import numpy as np
+    n = len(slices)
+    arr = (tvs_slice * n)()
+    total = 0
+    for i, sl in enumerate(slices):
+        arr[i] = tvs_slice(int(sl["H"]), int(sl["W"]), int(sl["offset"]), float(sl["alpha"]),
+                           float(sl["p"]), int(sl["seed"]), int(sl["stream_id"]))
+        total = max(total, int(sl["offset"]) + int(sl["H"]) * int(sl["W"]))
+    d = _dtype_code(x_pool)
+    for t, need in ((b_pool, total), (x_pool, total), (h_pool, total), (q_pool, 2 * total)):
+        if t.numel() < need:
+            raise ValueError(f"pool has {t.numel()} elements, {need} needed")
+        _ptr(t, None, d)
+    P = tvs_batch_params(step=float(step), outer_iters=int(outer_iters),
+                         inner_iters=int(inner_iters), nonneg=int(nonneg), k0=int(k0),
+                         flags=TVS_FLAG_GRAPH if graph else 0, fgp_variant=int(fgp_variant))
+    nprox = np.zeros(n, dtype=np.int64)
+    check(lib().tvs_proxskip_batched(C.c_void_p(ctx), d, n, arr, _ptr(b_pool), _ptr(x_pool),
+                                     _ptr(h_pool), _ptr(q_pool), C.byref(P),
+                                     nprox.ctypes.data_as(C.POINTER(C.c_int64))))
+    return nprox
+
+
+def tvs_fgp_set_variant_batched(ctx: int, dtype: int, n_slices: int, index: int) -> None:
+    check(lib().tvs_fgp_set_variant_batched(C.c_void_p(ctx), int(dtype), int(n_slices), int(index)))

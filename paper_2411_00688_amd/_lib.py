@@ -39,6 +39,17 @@ class tvs_report(C.Structure):
     _fields_ = [("n_prox", C.c_int64), ("iters", C.c_int64)]
 
 
+class tvs_slice(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("offset", C.c_int64), ("alpha", C.c_double),
+                ("p", C.c_double), ("seed", C.c_uint64), ("stream_id", C.c_uint64)]
+
+
+class tvs_batch_params(C.Structure):
+    _fields_ = [("step", C.c_double), ("outer_iters", C.c_int64), ("inner_iters", C.c_int32),
+                ("nonneg", C.c_int32), ("k0", C.c_int64), ("flags", C.c_int32),
+                ("fgp_variant", C.c_int32)]
+
+
 _lib = None
 
 vp = C.c_void_p
@@ -76,6 +87,9 @@ PROTOTYPES = {
     "tvs_fgp_variant": (C.c_int, [C.c_int, ip, ip, ip]),
     "tvs_fgp_set_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int]),
     "tvs_fgp_autotune": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, ip, dp]),
+    "tvs_proxskip_batched": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(tvs_slice), vp, vp, vp, vp,
+                                       C.POINTER(tvs_batch_params), C.POINTER(C.c_int64)]),
+    "tvs_fgp_set_variant_batched": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
 }
 
 

@@ -115,9 +115,16 @@ FgpConfig fgp_config(tvs_ctx* ctx, int H, int W, int dtype_bytes) {
     FgpConfig c;
     auto it = ctx->fgp_tuned.find(fgp_key(H, W, dtype_bytes));
     if (it != ctx->fgp_tuned.end()) return it->second;
-    c.tile_w = 32;
-    c.tile_h = 32;
-    c.steps = dtype_bytes == 4 ? 4 : 4;
+    if (H == 0) {
+        // batched form (key (0, n_slices)): large total sizes favour wide tiles
+        c.tile_w = 64;
+        c.tile_h = 16;
+        c.steps = 4;
+    } else {
+        c.tile_w = 32;
+        c.tile_h = 32;
+        c.steps = 4;
+    }
     return c;
 }
 

@@ -42,7 +42,11 @@ void graph_cache_clear(tvs_ctx* ctx) {
 
 void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void* b,
                const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue) {
-    const std::vector<uint64_t> key = make_key(op, pdhg, dtype, b, st, P);
+    graph_run_key(ctx, make_key(op, pdhg, dtype, b, st, P), enqueue);
+}
+
+void graph_run_key(tvs_ctx* ctx, const std::vector<uint64_t>& key,
+                   const std::function<void()>& enqueue) {
     for (GraphEntry* e : ctx->graphs) {
         if (e->key == key) {
             TVS_HIP(hipGraphLaunch(e->exec, ctx->stream));

@@ -70,8 +70,10 @@ enum : int {
     F_OUT = 128     // in the central tile and inside the image (stored)
 };
 
+// One output tile (tile row ty, tile column tx) of one image.  v, qa, qb, oa,
+// ob point at the image's data (dual planes [2][H][W] at qa etc.).
 template <typename T, int BW, int BH, int TS>
-__global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
+__device__ __forceinline__ void fgp_tile(const FgpArgs<T>& a, int ty, int tx) {
     constexpr int NT = 256;
     constexpr int RW = BW + 2 * TS, RH = BH + 2 * TS, R = RW * RH;
     constexpr int PPT = (R + NT - 1) / NT;
@@ -80,8 +82,8 @@ __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
     __shared__ T s_z[R];
 
     const int H = a.H, W = a.W;
-    const int i0 = (int)blockIdx.y * BH - TS;
-    const int j0 = (int)blockIdx.x * BW - TS;
+    const int i0 = ty * BH - TS;
+    const int j0 = tx * BW - TS;
     const int tid = (int)threadIdx.x;
 
     T qay[PPT], qax[PPT], qby[PPT], qbx[PPT], vv[PPT], ry[PPT], rx[PPT], zz[PPT];
@@ -181,6 +183,56 @@ __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
     }
 }
 
+template <typename T, int BW, int BH, int TS>
+__global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
+    fgp_tile<T, BW, BH, TS>(a, (int)blockIdx.y, (int)blockIdx.x);
+}
+
+// Batched form: block b of the launch works on tile (b - prefix[i]) of slice
+// act[i], where prefix holds the cumulative tile counts of the active
+// slices (binary search).  Each slice has its own size, offset and lambda.
+template <typename T>
+struct FgpBatchArgs {
+    FgpArgs<T> pools;     // v, qa, qb, oa, ob of the pools; beta, k_start, nsteps, nonneg
+    const BSlice<T>* sl;
+    const int* act;
+    const int* prefix;
+    int n_act;
+};
+
+__device__ __forceinline__ int find_item(const int* prefix, int n, int b) {
+    int lo = 0, hi = n;  // prefix[lo] <= b < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int BW, int BH, int TS>
+__global__ __launch_bounds__(256) void fgp_tb_batched_kernel(FgpBatchArgs<T> a) {
+    const int b = (int)blockIdx.x;
+    const int i = find_item(a.prefix, a.n_act, b);
+    const BSlice<T> sl = a.sl[a.act[i]];
+    const int t = b - a.prefix[i];
+    const int tiles_x = div_up(sl.W, BW);
+    FgpArgs<T> f = a.pools;
+    const size_t off = (size_t)sl.off;
+    f.v = a.pools.v + off;
+    f.qa = a.pools.qa + 2 * off;
+    f.qb = a.pools.qb + 2 * off;
+    f.oa = a.pools.oa + 2 * off;
+    f.ob = a.pools.ob ? a.pools.ob + 2 * off : nullptr;
+    f.lam = sl.lam;
+    f.H = sl.H;
+    f.W = sl.W;
+    f.plane = (size_t)sl.H * sl.W;
+    fgp_tile<T, BW, BH, TS>(f, t / tiles_x, t % tiles_x);
+}
+
 // ----------------------------------------------------------------- configs
 // Tile shapes compiled in; the autotuner (or the default) picks one by index.
 struct FgpVariant {
@@ -276,6 +328,68 @@ T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int
     return qa;
 }
 
+template <typename T>
+static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blocks, hipStream_t st) {
+    const FgpVariant& V = kFgpVariants[vi];
+#define TVS_FGPB(BW_, BH_, TS_)                                                                  \
+    if (V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                             \
+        hipLaunchKernelGGL((fgp_tb_batched_kernel<T, BW_, BH_, TS_>), dim3(blocks), dim3(256), 0, \
+                           st, a);                                                               \
+        return;                                                                                  \
+    }
+    TVS_FGPB(32, 32, 1) TVS_FGPB(32, 32, 2) TVS_FGPB(32, 32, 4) TVS_FGPB(32, 32, 8)
+    TVS_FGPB(64, 16, 1) TVS_FGPB(64, 16, 4) TVS_FGPB(64, 32, 4) TVS_FGPB(16, 16, 4)
+    if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
+#undef TVS_FGPB
+    throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
+}
+
+// FGP on every active slice of one batched iteration, with the same buffer
+// rotation as run_fgp; returns the pool holding the final duals.
+template <typename T>
+T* run_fgp_batched(tvs_ctx* ctx, const BSlice<T>* sl, const BatchLists& L, const T* v_pool,
+                   T* q_pool, size_t total_px, int iters, int nonneg, const FgpConfig& cfg) {
+    const int vi = find_variant(cfg, (int)sizeof(T));
+    const int TS = kFgpVariants[vi].ts;
+    T* bufs[4] = {q_pool, (T*)scratch(ctx, S_Q1, 2 * total_px * sizeof(T)),
+                  (T*)scratch(ctx, S_Q2, 2 * total_px * sizeof(T)),
+                  (T*)scratch(ctx, S_Q3, 2 * total_px * sizeof(T))};
+    const T* beta = beta_table_dev<T>(ctx, iters + 1);
+    T* qa = q_pool;
+    T* qb = q_pool;
+    int k = 0;
+    while (k < iters) {
+        const int ns = (iters - k) < TS ? (iters - k) : TS;
+        T* outs[2];
+        int n = 0;
+        for (int b = 0; b < 4 && n < 2; ++b)
+            if (bufs[b] != qa && bufs[b] != qb) outs[n++] = bufs[b];
+        FgpBatchArgs<T> a;
+        a.pools.v = v_pool;
+        a.pools.qa = qa;
+        a.pools.qb = qb;
+        a.pools.oa = outs[0];
+        a.pools.ob = ns > 1 ? outs[1] : nullptr;
+        a.pools.beta = beta;
+        a.pools.k_start = k;
+        a.pools.nsteps = ns;
+        a.pools.lam = T(0);
+        a.pools.nonneg = nonneg;
+        a.pools.H = a.pools.W = 0;
+        a.pools.plane = 0;
+        a.sl = sl;
+        a.act = L.act;
+        a.prefix = L.pref_fgp;
+        a.n_act = L.n_act;
+        launch_fgp_batched_variant<T>(vi, a, L.tiles_fgp, ctx->stream);
+        TVS_LAUNCH_CHECK();
+        qb = ns > 1 ? outs[1] : qa;
+        qa = outs[0];
+        k += ns;
+    }
+    return qa;
+}
+
 // -------------------------------------------------------------- finalize
 // z = P_X(v + div q) and the bookkeeping that follows a prox evaluation.
 // 32 x 32 tiles, 256 threads (4 pixels each); the transposed copy of xbar
@@ -339,6 +453,52 @@ void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f) {
     TVS_LAUNCH_CHECK();
 }
 
+// Batched finalize (ProxSkip bookkeeping) over the active slices' 32 x 32 tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void finalize_batched_kernel(const BSlice<T>* sl, BatchLists L,
+                                                              const T* v, const T* q, T* q_out,
+                                                              T* x, T* h, const T* xhat,
+                                                              int nonneg) {
+    const int b = (int)blockIdx.x;
+    const int it = find_item(L.pref_fin, L.n_act, b);
+    const BSlice<T> S = sl[L.act[it]];
+    const int t = b - L.pref_fin[it];
+    const int tiles_x = div_up(S.W, 32);
+    const int i0 = (t / tiles_x) * 32, j0 = (t % tiles_x) * 32;
+    const int H = S.H, W = S.W;
+    const size_t off = (size_t)S.off, plane = (size_t)H * W;
+    const T* qy = q + 2 * off;
+    const T* qx = qy + plane;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int i = i0 + idx / 32, j = j0 + idx % 32;
+        if (i >= H || j >= W) continue;
+        const size_t g = (size_t)i * W + j;
+        T d = T(0);
+        if (i < H - 1) d += qy[g];
+        if (i > 0) d -= qy[g - W];
+        if (j < W - 1) d += qx[g];
+        if (j > 0) d -= qx[g - 1];
+        T z = v[off + g] + d;
+        if (nonneg) z = (z > T(0)) ? z : T(0);
+        if (q_out != q) {
+            q_out[2 * off + g] = qy[g];
+            q_out[2 * off + plane + g] = qx[g];
+        }
+        h[off + g] = h[off + g] + S.rate * (z - xhat[off + g]);
+        x[off + g] = z;
+    }
+}
+
+template <typename T>
+void launch_finalize_batched(tvs_ctx* ctx, const BSlice<T>* sl, const BatchLists& L, const T* v,
+                             const T* q, T* q_out, T* x, T* h, const T* xhat, int nonneg) {
+    hipLaunchKernelGGL((finalize_batched_kernel<T>), dim3(L.tiles_fin), dim3(256), 0, ctx->stream,
+                       sl, L, v, q, q_out, x, h, xhat, nonneg);
+    TVS_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------- grad / div
 template <typename T>
 __global__ void grad_kernel(int H, int W, const T* u, T* q) {
@@ -390,6 +550,10 @@ void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T* u) {
 
 #define TVS_INST(T)                                                                          \
     template T* run_fgp<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, const FgpConfig&); \
+    template T* run_fgp_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&, const T*, T*,   \
+                                   size_t, int, int, const FgpConfig&);                          \
+    template void launch_finalize_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&,      \
+                                             const T*, const T*, T*, T*, T*, const T*, int);     \
     template void launch_finalize<T>(tvs_ctx*, int, int, const Finalize<T>&);                \
     template void launch_grad<T>(tvs_ctx*, int, int, const T*, T*);                          \
     template void launch_div<T>(tvs_ctx*, int, int, const T*, T*);

@@ -184,6 +184,59 @@ void launch_dual_prox_pointwise(tvs_ctx* ctx, size_t n, const T* xb, const T* b,
     TVS_LAUNCH_CHECK();
 }
 
+// Batched ProxSkip data step for A = I over all slices' 32 x 32 tiles (block
+// b -> slice by binary search of the cumulative tile counts pref_all).
+__device__ __forceinline__ int find_item_ops(const int* prefix, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void identity_step_batched_kernel(
+    const BSlice<T>* sl, const int* pref_all, int n, const uint8_t* theta, const T* b, T* x,
+    const T* h, T* xhat, T* v, T step) {
+    const int blk = (int)blockIdx.x;
+    const int s = find_item_ops(pref_all, n, blk);
+    const BSlice<T> S = sl[s];
+    const int t = blk - pref_all[s];
+    const int tiles_x = div_up(S.W, 32);
+    const int i0 = (t / tiles_x) * 32, j0 = (t % tiles_x) * 32;
+    const int th = theta[s];
+    const size_t off = (size_t)S.off;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int i = i0 + idx / 32, j = j0 + idx % 32;
+        if (i >= S.H || j >= S.W) continue;
+        const size_t g = off + (size_t)i * S.W + j;
+        const T xv = x[g], hv = h[g];
+        const T w = xv - step * (xv - b[g]);
+        const T xh = w + step * hv;
+        if (th) {
+            v[g] = w + S.coef * hv;
+            xhat[g] = xh;
+        } else {
+            x[g] = xh;
+        }
+    }
+}
+
+template <typename T>
+void launch_identity_step_batched(tvs_ctx* ctx, const BSlice<T>* sl, const int* pref_all, int n,
+                                  int tiles, const uint8_t* theta, const T* b, T* x, const T* h,
+                                  T* xhat, T* v, T step) {
+    hipLaunchKernelGGL((identity_step_batched_kernel<T>), dim3(tiles), dim3(256), 0, ctx->stream,
+                       sl, pref_all, n, theta, b, x, h, xhat, v, step);
+    TVS_LAUNCH_CHECK();
+}
+
 // -------------------------------------------------------------------- blur
 enum BlurMode { BLUR_STORE = 0, BLUR_RESIDUAL = 1, BLUR_DUAL_PROX = 2, BLUR_PRIMAL = 3 };
 
@@ -857,6 +910,8 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     template void launch_blur_adjoint_step<T>(tvs_ctx*, const tvs_op*, const T*, const PrimalStep<T>&); \
     template void launch_joseph_fwd<T>(tvs_ctx*, const tvs_op*, const T*, const T*, const T*, T*, int, T); \
     template void launch_pad_copy<T>(tvs_ctx*, int, int, const T*, T*, T*);                      \
+    template void launch_identity_step_batched<T>(tvs_ctx*, const BSlice<T>*, const int*, int, int, \
+                                                  const uint8_t*, const T*, T*, const T*, T*, T*, T); \
     template void launch_joseph_adj<T>(tvs_ctx*, const tvs_op*, const T*, T*, const PrimalStep<T>*);
 TVS_INST(float)
 TVS_INST(double)

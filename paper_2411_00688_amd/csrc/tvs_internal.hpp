@@ -51,7 +51,7 @@ struct Scratch {
 enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
     S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
-    S_PADX, S_COUNT
+    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_COUNT
 };
 
 struct GraphEntry;
@@ -140,6 +140,16 @@ struct tvs_op {
 };
 
 namespace tvs {
+
+// One slice of the batched form: size, element offset in the pools (the
+// slice's dual planes start at 2 * off in the dual pool) and its per-slice
+// scalars lambda = alpha gamma / p, coef = gamma - gamma / p, rate = p / gamma.
+template <typename T>
+struct BSlice {
+    int H, W;
+    long long off;
+    T lam, coef, rate;
+};
 
 // ---------------------------------------------------------------- epilogues
 // What a per-pixel data-fidelity kernel does with s = (grad f) or (A^T y) at
@@ -261,11 +271,31 @@ const double* beta_table_host(int n);
 
 template <typename T> const T* beta_table_dev(tvs_ctx* ctx, int n);
 
+// batched form (kernels_fgp.hip, kernels_ops.hip)
+struct BatchLists {
+    const int* act;         // active slice ids of this iteration
+    const int* pref_fgp;    // cumulative FGP tile counts (n_act + 1)
+    const int* pref_fin;    // cumulative 32 x 32 tile counts (n_act + 1)
+    int n_act, tiles_fgp, tiles_fin;
+};
+template <typename T>
+T* run_fgp_batched(tvs_ctx* ctx, const BSlice<T>* sl, const BatchLists& L, const T* v_pool,
+                   T* q_pool, size_t total_px, int iters, int nonneg, const FgpConfig& cfg);
+template <typename T>
+void launch_finalize_batched(tvs_ctx* ctx, const BSlice<T>* sl, const BatchLists& L, const T* v,
+                             const T* q, T* q_out, T* x, T* h, const T* xhat, int nonneg);
+template <typename T>
+void launch_identity_step_batched(tvs_ctx* ctx, const BSlice<T>* sl, const int* pref_all, int n,
+                                  int tiles, const uint8_t* theta, const T* b, T* x, const T* h,
+                                  T* xhat, T* v, T step);
+
 // graphs (graph.hip)
 // Runs `enqueue` captured into a HIP graph (cached under the call's key) on
 // ctx->stream.  All scratch memory must already be allocated.
 void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void* b,
                const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue);
+void graph_run_key(tvs_ctx* ctx, const std::vector<uint64_t>& key,
+                   const std::function<void()>& enqueue);
 void graph_cache_clear(tvs_ctx* ctx);
 
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }

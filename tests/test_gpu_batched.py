@@ -1,0 +1,160 @@
+"""GPU tests of the batched ProxSkip form (many uneven TV-denoising slices).
+
+Every slice must equal a separate single-image tvs_proxskip call with the
+same parameters bit for bit (same per-pixel arithmetic), and the float64
+batch must match the oracle; graph replays must repeat the stream result.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2411_00688_amd as T
+import synth
+from gpu_util import F32, F64, as_input, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(20, 33), (64, 64), (100, 37), (1, 50), (128, 128), (45, 45), (37, 1)]
+
+
+def make_batch(sizes, dtype, seed0=50):
+    slices, bs = [], []
+    off = 0
+    rng = np.random.default_rng(seed0)
+    for s, (H, W) in enumerate(sizes):
+        u, eta = synth.phantom_and_noise(H, W, 5, seed0 + s, (H, W))
+        sigma = rng.uniform(0.02, 0.1)
+        b = as_input(u + sigma * eta, dtype)
+        slices.append(dict(H=H, W=W, offset=off, alpha=2 * sigma, p=rng.uniform(0.05, 0.5),
+                           seed=1234 + s, stream_id=s))
+        bs.append(b)
+        off += H * W + 7  # gaps between slices are allowed
+    return slices, bs, off
+
+
+def pools(bs, slices, total, dt):
+    b = torch.zeros(total, dtype=dt, device="cuda")
+    for sl, bb in zip(slices, bs):
+        b[sl["offset"]:sl["offset"] + sl["H"] * sl["W"]] = torch.tensor(bb.ravel(), dtype=dt)
+    x = torch.zeros(total, dtype=dt, device="cuda")
+    h = torch.zeros_like(x)
+    q = torch.zeros(2 * total, dtype=dt, device="cuda")
+    return b, x, h, q
+
+
+def slice_of(pool, sl, planes=1):
+    n = sl["H"] * sl["W"]
+    o = planes * sl["offset"]
+    return pool[o:o + planes * n].view(planes, sl["H"], sl["W"]) if planes > 1 else \
+        pool[o:o + n].view(sl["H"], sl["W"])
+
+
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_batched_equals_single_slice_solves(ctx, dt):
+    slices, bs, total = make_batch(SIZES, dt)
+    b, x, h, q = pools(bs, slices, total, dt)
+    K, Kin = 40, 12
+    nprox = T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, K, Kin)
+    for sl, bb, npx in zip(slices, bs, nprox):
+        H, W = sl["H"], sl["W"]
+        op = T.tvs_op_identity(ctx, H, W)
+        try:
+            xs = torch.zeros(H, W, dtype=dt, device="cuda")
+            hs = torch.zeros_like(xs)
+            qs = torch.zeros(2, H, W, dtype=dt, device="cuda")
+            r = T.tvs_proxskip(op, torch.tensor(bb, dtype=dt, device="cuda"), xs, hs, qs,
+                               sl["alpha"], 1.0, sl["p"], K, Kin, seed=sl["seed"],
+                               stream_id=sl["stream_id"])
+            assert r["n_prox"] == npx
+            assert torch.equal(slice_of(x, sl), xs)
+            assert torch.equal(slice_of(h, sl), hs)
+            assert torch.equal(slice_of(q, sl, 2), qs)
+        finally:
+            T.tvs_op_destroy(op)
+
+
+def test_batched_f64_matches_oracle(ctx):
+    slices, bs, total = make_batch(SIZES[:5], F64, seed0=70)
+    b, x, h, q = pools(bs, slices, total, F64)
+    K, Kin = 60, 20
+    T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, K, Kin)
+    for sl, bb in zip(slices, bs):
+        ref = O.proxskip(O.identity(sl["H"], sl["W"]), bb, sl["alpha"], 1.0, sl["p"], K, Kin,
+                         seed=sl["seed"], stream=sl["stream_id"])
+        assert rel_l2(host(slice_of(x, sl)), ref["x"]) < 1e-10
+        assert rel_l2(host(slice_of(q, sl, 2)), ref["q"]) < 1e-10
+
+
+def test_batched_graph_replays(ctx):
+    slices, bs, total = make_batch(SIZES, F32, seed0=90)
+    b, x, h, q = pools(bs, slices, total, F32)
+    T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, 30, 10)
+    ref = x.clone()
+    for rep in range(3):
+        for t in (x, h, q):
+            t.zero_()
+        T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, 30, 10, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref), f"replay {rep}"
+        _ = (torch.randn(4096, device="cuda") + 1).sum().item()
+
+
+def test_batched_rejects_overlap_and_bad_p(ctx):
+    sl = [dict(H=8, W=8, offset=0, alpha=0.1, p=0.5, seed=1, stream_id=0),
+          dict(H=8, W=8, offset=10, alpha=0.1, p=0.5, seed=1, stream_id=1)]
+    b = torch.zeros(200, device="cuda")
+    with pytest.raises(T.TvsError):
+        T.tvs_proxskip_batched(ctx, sl, b, b.clone(), b.clone(), torch.zeros(400, device="cuda"),
+                               1.0, 2, 2)
+    sl[1]["offset"] = 64
+    sl[1]["p"] = 0.0
+    with pytest.raises(T.TvsError):
+        T.tvs_proxskip_batched(ctx, sl, b, b.clone(), b.clone(), torch.zeros(400, device="cuda"),
+                               1.0, 2, 2)
+
+
+def test_batched_full_workload_sampled(ctx):
+    """The 256-slice batched workload at full size (sizes 128..1024, 500
+    outer iterations, 50 FGP iterations): the smallest slice against the
+    oracle, two slices against separate single-image GPU solves (bitwise)."""
+    sl_params = synth.batched_slices()
+    slices, off = [], 0
+    for sp in sl_params:
+        slices.append(dict(H=sp["H"], W=sp["W"], offset=off, alpha=sp["alpha"], p=sp["p"],
+                           seed=sp["seed"], stream_id=sp["stream"]))
+        off += sp["H"] * sp["W"]
+    total = off
+    b = torch.empty(total, dtype=F32, device="cuda")
+    bs = {}
+    pick = [min(range(len(slices)), key=lambda i: slices[i]["H"]),
+            max(range(len(slices)), key=lambda i: slices[i]["H"]), 100]
+    for i, (sl, sp) in enumerate(zip(slices, sl_params)):
+        u, eta = synth.batched_slice_inputs(sp)
+        bb = as_input(u + sp["sigma"] * eta, F32)
+        if i in pick:
+            bs[i] = bb
+        b[sl["offset"]:sl["offset"] + sl["H"] * sl["W"]] = torch.tensor(bb.ravel(), dtype=F32)
+    x = torch.zeros(total, dtype=F32, device="cuda")
+    h = torch.zeros_like(x)
+    q = torch.zeros(2 * total, dtype=F32, device="cuda")
+    K, Kin = 500, 50
+    T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, K, Kin, graph=True)
+    torch.cuda.synchronize()
+    i0 = pick[0]
+    sl = slices[i0]
+    ref = O.proxskip(O.identity(sl["H"], sl["W"]), bs[i0], sl["alpha"], 1.0, sl["p"], K, Kin,
+                     seed=sl["seed"], stream=sl["stream_id"])
+    assert rel_l2(host(slice_of(x, sl)), ref["x"]) < 1e-3
+    for i in pick[1:]:
+        sl = slices[i]
+        op = T.tvs_op_identity(ctx, sl["H"], sl["W"])
+        try:
+            xs = torch.zeros(sl["H"], sl["W"], dtype=F32, device="cuda")
+            hs, qs = torch.zeros_like(xs), torch.zeros(2, sl["H"], sl["W"], dtype=F32, device="cuda")
+            T.tvs_proxskip(op, torch.tensor(bs[i], dtype=F32, device="cuda"), xs, hs, qs,
+                           sl["alpha"], 1.0, sl["p"], K, Kin, seed=sl["seed"],
+                           stream_id=sl["stream_id"])
+            assert torch.equal(slice_of(x, sl), xs)
+        finally:
+            T.tvs_op_destroy(op)
