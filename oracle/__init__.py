@@ -20,6 +20,11 @@ Parity status of each function (what pins it lives in tests/test_oracle_*.py):
   op_norm ......................... pinned (identity, blur = 1, SVD of small A)
   pdhg_explicit ................... pinned (agrees with PGD/PDHG minimisers and
                                      with the exact 1-D/2-pixel solutions)
+  cnn_forward ..................... pinned (layers against scipy correlate2d,
+                                     head closed form with zero weights)
+  cnn_loss_grad ................... pinned (central finite differences)
+  adam_step ....................... pinned (first step = -lr sign(g); constant-
+                                     gradient closed form)
 """
 
 from __future__ import annotations
@@ -88,6 +93,13 @@ def lib():
         L.orc_op_norm.restype = C.c_double
         L.orc_pdhg_explicit.argtypes = [C.POINTER(OrcOp), dp, C.c_double, C.c_int, C.c_int64,
                                         dp, dp, dp, C.c_int64, dp]
+        L.orc_cnn_param_count.argtypes = []
+        L.orc_cnn_param_count.restype = C.c_size_t
+        L.orc_cnn_forward.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
+        L.orc_cnn_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
+        L.orc_cnn_loss_grad.restype = C.c_double
+        L.orc_adam_step.argtypes = [C.c_size_t, dp, dp, dp, dp, C.c_int64, C.c_double,
+                                    C.c_double, C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -292,3 +304,49 @@ def pdhg_explicit(A: Op, b, alpha, nonneg, iters, x=None, y1=None, y2=None, obj_
     lib().orc_pdhg_explicit(C.byref(A.s), _p(b), float(alpha), int(nonneg), int(iters),
                             _p(x), _p(y1), _p(y2), int(obj_every), _p(obj))
     return dict(x=x, y1=y1, y2=y2, obj=obj[:nrec])
+
+
+# ---------------------------------------------------------------- learned prox
+def cnn_param_count() -> int:
+    return int(lib().orc_cnn_param_count())
+
+
+def _batch(v, lam):
+    v = _f64(v)
+    if v.ndim == 2:
+        v = v[None]
+    lam = _f64(np.broadcast_to(np.asarray(lam, dtype=np.float64), (v.shape[0],)))
+    return v, lam
+
+
+def cnn_forward(v, lam, params, nonneg=0):
+    """v: [n][H][W] (or [H][W]), lam: scalar or [n].  Returns (qt [n][2][H][W], z [n][H][W])."""
+    v, lam = _batch(v, lam)
+    n, H, W = v.shape
+    params = _f64(params)
+    assert params.size == cnn_param_count()
+    qt = np.empty((n, 2, H, W))
+    z = np.empty((n, H, W))
+    lib().orc_cnn_forward(n, H, W, _p(v), _p(lam), int(nonneg), _p(params), _p(qt), _p(z))
+    return qt, z
+
+
+def cnn_loss_grad(v, lam, params, z_target, nonneg=0, want_grad=True):
+    """Returns (loss, grad or None)."""
+    v, lam = _batch(v, lam)
+    n, H, W = v.shape
+    params = _f64(params)
+    zt = _f64(z_target).reshape(n, H, W)
+    g = np.empty(params.size) if want_grad else None
+    loss = lib().orc_cnn_loss_grad(n, H, W, _p(v), _p(lam), int(nonneg), _p(params), _p(zt),
+                                   _p(g) if want_grad else None)
+    return loss, g
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on params, m, v (float64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(grad)
+    lib().orc_adam_step(params.size, _p(params), _p(g), _p(m), _p(v), int(step), float(lr),
+                        float(beta1), float(beta2), float(eps))

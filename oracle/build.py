@@ -8,13 +8,13 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SRC = os.path.join(HERE, "oracle.c")
+SRCS = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "cnn.c")]
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-Wno-unused-parameter", *SRCS, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)

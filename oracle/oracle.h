@@ -100,6 +100,20 @@ void orc_pdhg_explicit(const orc_op* A, const double* b, double alpha,
                        int nonneg, int64_t iters, double* x, double* y1,
                        double* y2, int64_t obj_every, double* obj_trace);
 
+/* ---- learned TV prox (cnn.c): 2 -> 32 -> 32 -> 32 -> 2, 3x3, dual output ---- */
+#define ORC_CNN_LAYERS 4
+size_t orc_cnn_param_count(void);
+/* v: [n][H][W], lam: [n]; qt_out (nullable): [n][2][H][W] raw network output;
+ * z_out (nullable): [n][H][W] = P_X(v + div P_lam(qt)). */
+void orc_cnn_forward(int n, int H, int W, const double* v, const double* lam, int nonneg,
+                     const double* params, double* qt_out, double* z_out);
+/* Loss sum (z - z_target)^2 / (2 n H W) and its gradient (nullable). */
+double orc_cnn_loss_grad(int n, int H, int W, const double* v, const double* lam,
+                         int nonneg, const double* params, const double* z_target,
+                         double* grad);
+void orc_adam_step(size_t n, double* params, const double* grad, double* m, double* v,
+                   int64_t step, double lr, double beta1, double beta2, double eps);
+
 #ifdef __cplusplus
 }
 #endif
