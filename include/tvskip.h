@@ -266,6 +266,86 @@ tvs_status tvs_proxskip_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
  * slices in this context (-1 restores the default). */
 tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices, int index);
 
+/* ------------------------------------------------------------ learned prox
+ * A learned replacement for the inner TV-prox solver of Sec. 3 (the prox of
+ * eq. (3) with R = TV).  A 3x3 convolutional network, channels 2 -> 32 ->
+ * 32 -> 32 -> 2 with ReLU between layers and zero padding, maps the prox
+ * input v and a constant map of the prox weight lam to a dual field qt
+ * [2][H][W]; the prox output is recovered as the dual method recovers it
+ * (u = b + div q, Sec. 2.1, with the ball projection of eq. (7)):
+ *
+ *     q = P_lam(qt),   z = P_X(v + div q)      (P_X = max(., 0) if nonneg)
+ *
+ * so every prediction has an exact duality gap and is a valid warm start for
+ * FGP.  Convolutions run on the BF16 matrix cores with FP32 accumulation;
+ * the master parameters, the gradient and Adam run in FP32.  The CNN works
+ * on float32 data only.  The forward pass carries every operand as two BF16
+ * parts (x = hi + lo) and takes three products per K slice (hi hi, hi lo,
+ * lo hi), which brings its error near FP32's; the backward pass uses single
+ * BF16 operands.  tvs_cnn_set_fast_forward switches the forward and prox
+ * calls (not training) to single BF16 operands.
+ *
+ * Parameter vector (float32, tvs_cnn_param_count() = 19682 entries): for
+ * layer l = 1..4 with (C_in, C_out) = (2,32), (32,32), (32,32), (32,2):
+ * W_l[9][C_in][C_out] then b_l[C_out]; tap t = 3 * (row offset + 1) +
+ * (column offset + 1), out(p) = b + sum_t sum_ci W[t][ci][co] in(p + o_t).
+ *
+ * Batches: v, z_target [n][H][W] and qt [n][2][H][W] are float32 device
+ * buffers; lam_host is n doubles on the host.  Training loss:
+ * L = sum (z - z_target)^2 / (2 n H W).  A tvs_cnn belongs to one context
+ * and uses its stream; it owns its parameters and scratch (grow-only). */
+typedef struct tvs_cnn tvs_cnn;
+
+/* New network, He-normal weights from a counter-based generator keyed by
+ * seed (zero biases), Adam state cleared. */
+tvs_status tvs_cnn_create(tvs_ctx* ctx, uint64_t seed, tvs_cnn** out);
+void tvs_cnn_destroy(tvs_cnn* cnn);
+int64_t tvs_cnn_param_count(void);
+/* Copy the FP32 master parameters to / from host memory (param_count
+ * floats).  Setting parameters clears the Adam state and step count. */
+tvs_status tvs_cnn_get_params(tvs_cnn* cnn, float* params_host);
+tvs_status tvs_cnn_set_params(tvs_cnn* cnn, const float* params_host);
+/* Forward pass: qt_out (nullable) gets the raw network output, z_out
+ * (nullable) the prox estimate z.  Sizes: n >= 1, 1 <= H, W <= 32768,
+ * n H W <= 2^31. */
+tvs_status tvs_cnn_forward(tvs_cnn* cnn, int n, int H, int W, const float* v,
+                           const double* lam_host, int nonneg, float* qt_out, float* z_out);
+/* Loss (host, nullable) and its gradient with respect to the parameters
+ * (grad_out: device float32[param_count], nullable; the gradient is also kept
+ * for tvs_cnn_adam_step).  Synchronises when loss_out is set. */
+tvs_status tvs_cnn_loss_grad(tvs_cnn* cnn, int n, int H, int W, const float* v,
+                             const double* lam_host, int nonneg, const float* z_target,
+                             double* loss_out, float* grad_out);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) with the
+ * gradient grad (device float32[param_count]) or, when grad is NULL, the one
+ * kept by the last tvs_cnn_loss_grad. */
+tvs_status tvs_cnn_adam_step(tvs_cnn* cnn, const float* grad, double lr);
+/* tvs_cnn_loss_grad followed by tvs_cnn_adam_step. */
+tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
+                              const double* lam_host, int nonneg, const float* z_target,
+                              double lr, double* loss_out);
+/* Learned prox of one H x W image with a duality-gap gate: the network's
+ * dual q = P_lam(qt) is written to q_out [2][H][W]; if its relative gap
+ * gap(q) / P(z_q) (the gap of eq. (6) in the form gap(q) = sum_i lam
+ * |(D z_q)_i| - <(D z_q)_i, q_i>, P the prox objective) exceeds gap_tol and
+ * fallback_iters > 0, FGP runs fallback_iters iterations warm-started from q
+ * and q_out gets its final dual.  z_out gets P_X(v + div q_out).
+ * fell_back_out (nullable) is set to 1 when FGP ran; rel_gap_out (nullable)
+ * gets the network's relative gap.  Synchronises (the gate is decided on the
+ * host). */
+tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, int nonneg,
+                        double gap_tol, int fallback_iters, float* q_out, float* z_out,
+                        int* fell_back_out, double* rel_gap_out);
+/* fast != 0: tvs_cnn_forward and tvs_cnn_prox use single-part BF16
+ * operands (one product per K slice, about three times fewer matrix-core
+ * operations, BF16-level error); 0 (the default): two-part operands. */
+tvs_status tvs_cnn_set_fast_forward(tvs_cnn* cnn, int fast);
+/* Save / load the parameters as a little-endian binary file: the 8 bytes
+ * "TVSCNN01", an int64 parameter count, then the float32 parameters.
+ * Loading clears the Adam state; a file of another count is TVS_ERR_SHAPE. */
+tvs_status tvs_cnn_save(tvs_cnn* cnn, const char* path);
+tvs_status tvs_cnn_load(tvs_cnn* cnn, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,10 @@ __all__ = [
     "tvs_proxskip", "tvs_pdhgskip",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
     "tvs_proxskip_batched", "tvs_fgp_set_variant_batched",
+    "tvs_cnn_create", "tvs_cnn_destroy", "tvs_cnn_param_count", "tvs_cnn_get_params",
+    "tvs_cnn_set_params", "tvs_cnn_forward", "tvs_cnn_loss_grad", "tvs_cnn_adam_step",
+    "tvs_cnn_train_step", "tvs_cnn_prox", "tvs_cnn_set_fast_forward", "tvs_cnn_save",
+    "tvs_cnn_load",
 ]
 
 
@@ -285,3 +289,115 @@ def tvs_proxskip_batched(ctx: int, slices, b_pool, x_pool, h_pool, q_pool, step,
 
 def tvs_fgp_set_variant_batched(ctx: int, dtype: int, n_slices: int, index: int) -> None:
     check(lib().tvs_fgp_set_variant_batched(C.c_void_p(ctx), int(dtype), int(n_slices), int(index)))
+
+
+# ---------------------------------------------------------------- learned prox
+def _lam_array(lam, n):
+    try:
+        vals = [float(x) for x in lam]
+    except TypeError:
+        vals = [float(lam)] * n
+    if len(vals) != n:
+        raise ValueError(f"{len(vals)} lam values for a batch of {n}")
+    return (C.c_double * n)(*vals)
+
+
+def _batch_shape(v):
+    if v.dim() == 2:
+        return 1, v.shape[0], v.shape[1]
+    if v.dim() == 3:
+        return v.shape[0], v.shape[1], v.shape[2]
+    raise ValueError("v must be (H, W) or (n, H, W)")
+
+
+def _f32(t):
+    import torch
+    if t is not None and t.dtype != torch.float32:
+        raise TypeError("the learned prox works on float32 tensors")
+    return t
+
+
+def tvs_cnn_param_count() -> int:
+    return int(lib().tvs_cnn_param_count())
+
+
+def tvs_cnn_create(ctx: int, seed: int = 0) -> int:
+    out = C.c_void_p()
+    check(lib().tvs_cnn_create(C.c_void_p(ctx), int(seed), C.byref(out)))
+    return out.value
+
+
+def tvs_cnn_destroy(cnn: int) -> None:
+    lib().tvs_cnn_destroy(C.c_void_p(cnn))
+
+
+def tvs_cnn_get_params(cnn: int):
+    import numpy as np
+    p = np.empty(tvs_cnn_param_count(), dtype=np.float32)
+    check(lib().tvs_cnn_get_params(C.c_void_p(cnn), C.c_void_p(p.ctypes.data)))
+    return p
+
+
+def tvs_cnn_set_params(cnn: int, params) -> None:
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != tvs_cnn_param_count():
+        raise ValueError(f"{p.size} parameters, {tvs_cnn_param_count()} expected")
+    check(lib().tvs_cnn_set_params(C.c_void_p(cnn), C.c_void_p(p.ctypes.data)))
+
+
+def tvs_cnn_forward(cnn: int, v, lam, nonneg: int = 0, qt=None, z=None) -> None:
+    """v (n,H,W) or (H,W) float32; lam scalar or n values; fills qt (n,2,H,W)
+    and/or z (same shape as v)."""
+    n, H, W = _batch_shape(_f32(v))
+    check(lib().tvs_cnn_forward(C.c_void_p(cnn), n, H, W, _ptr(v), _lam_array(lam, n),
+                                int(nonneg), _ptr(_f32(qt), 2 * n * H * W),
+                                _ptr(_f32(z), n * H * W)))
+
+
+def tvs_cnn_loss_grad(cnn: int, v, lam, z_target, nonneg: int = 0, grad=None) -> float:
+    n, H, W = _batch_shape(_f32(v))
+    loss = C.c_double()
+    check(lib().tvs_cnn_loss_grad(C.c_void_p(cnn), n, H, W, _ptr(v), _lam_array(lam, n),
+                                  int(nonneg), _ptr(_f32(z_target), n * H * W), C.byref(loss),
+                                  _ptr(_f32(grad), tvs_cnn_param_count())))
+    return loss.value
+
+
+def tvs_cnn_adam_step(cnn: int, lr: float, grad=None) -> None:
+    check(lib().tvs_cnn_adam_step(C.c_void_p(cnn), _ptr(_f32(grad), tvs_cnn_param_count()),
+                                  float(lr)))
+
+
+def tvs_cnn_train_step(cnn: int, v, lam, z_target, lr: float, nonneg: int = 0,
+                       want_loss: bool = True):
+    n, H, W = _batch_shape(_f32(v))
+    loss = C.c_double()
+    check(lib().tvs_cnn_train_step(C.c_void_p(cnn), n, H, W, _ptr(v), _lam_array(lam, n),
+                                   int(nonneg), _ptr(_f32(z_target), n * H * W), float(lr),
+                                   C.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def tvs_cnn_prox(cnn: int, v, lam: float, nonneg: int, gap_tol: float, fallback_iters: int,
+                 q, z):
+    """Gap-gated learned prox of one image.  Returns (fell_back, rel_gap)."""
+    H, W = _f32(v).shape
+    fb = C.c_int()
+    rg = C.c_double()
+    check(lib().tvs_cnn_prox(C.c_void_p(cnn), H, W, _ptr(v), float(lam), int(nonneg),
+                             float(gap_tol), int(fallback_iters), _ptr(_f32(q), 2 * H * W),
+                             _ptr(_f32(z), H * W), C.byref(fb), C.byref(rg)))
+    return bool(fb.value), rg.value
+
+
+def tvs_cnn_set_fast_forward(cnn: int, fast: bool) -> None:
+    check(lib().tvs_cnn_set_fast_forward(C.c_void_p(cnn), int(bool(fast))))
+
+
+def tvs_cnn_save(cnn: int, path: str) -> None:
+    check(lib().tvs_cnn_save(C.c_void_p(cnn), str(path).encode()))
+
+
+def tvs_cnn_load(cnn: int, path: str) -> None:
+    check(lib().tvs_cnn_load(C.c_void_p(cnn), str(path).encode()))

@@ -90,6 +90,21 @@ PROTOTYPES = {
     "tvs_proxskip_batched": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(tvs_slice), vp, vp, vp, vp,
                                        C.POINTER(tvs_batch_params), C.POINTER(C.c_int64)]),
     "tvs_fgp_set_variant_batched": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+    "tvs_cnn_create": (C.c_int, [vp, C.c_uint64, C.POINTER(vp)]),
+    "tvs_cnn_destroy": (None, [vp]),
+    "tvs_cnn_param_count": (C.c_int64, []),
+    "tvs_cnn_get_params": (C.c_int, [vp, vp]),
+    "tvs_cnn_set_params": (C.c_int, [vp, vp]),
+    "tvs_cnn_forward": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, vp]),
+    "tvs_cnn_loss_grad": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, dp, vp]),
+    "tvs_cnn_adam_step": (C.c_int, [vp, vp, C.c_double]),
+    "tvs_cnn_train_step": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp,
+                                     C.c_double, dp]),
+    "tvs_cnn_prox": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_double, C.c_int, C.c_double,
+                               C.c_int, vp, vp, ip, dp]),
+    "tvs_cnn_set_fast_forward": (C.c_int, [vp, C.c_int]),
+    "tvs_cnn_save": (C.c_int, [vp, C.c_char_p]),
+    "tvs_cnn_load": (C.c_int, [vp, C.c_char_p]),
 }
 
 

@@ -462,7 +462,7 @@ extern "C" tvs_status tvs_div(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const
 namespace tvs {
 
 template <typename T>
-static void gap_host(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, const T* q,
+void gap_host(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, const T* q,
                      double* gap, double* primal) {
     const size_t n = (size_t)H * W;
     T* z = (T*)scratch(ctx, S_Z, n * sizeof(T));
@@ -484,7 +484,7 @@ static void gap_host(tvs_ctx* ctx, int H, int W, const T* v, double lam, int non
 }
 
 template <typename T>
-static void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters,
+void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters,
                          int nonneg, T* q, T* z, double* rel_gap) {
     const FgpConfig cfg = fgp_config(ctx, H, W, (int)sizeof(T));
     T* qf = run_fgp<T>(ctx, H, W, v, lambda, iters, nonneg, q, cfg);
@@ -502,6 +502,11 @@ static void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, 
         *rel_gap = pr > 0 ? g / pr : g;
     }
 }
+
+template void gap_host<float>(tvs_ctx*, int, int, const float*, double, int, const float*,
+                              double*, double*);
+template void tv_prox_impl<float>(tvs_ctx*, int, int, const float*, double, int, int, float*,
+                                  float*, double*);
 
 }  // namespace tvs
 

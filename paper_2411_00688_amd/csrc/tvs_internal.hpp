@@ -298,6 +298,73 @@ void graph_run_key(tvs_ctx* ctx, const std::vector<uint64_t>& key,
                    const std::function<void()>& enqueue);
 void graph_cache_clear(tvs_ctx* ctx);
 
+// TV prox and its duality gap on one image (api.hip); gap_host synchronises
+template <typename T>
+void gap_host(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, const T* q,
+              double* gap, double* primal);
+template <typename T>
+void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
+                  T* q, T* z, double* rel_gap);
+
+// learned prox (kernels_cnn.hip)
+namespace cnn {
+constexpr int CONV_NT = 256;   // threads per block of the convolution kernels
+constexpr int CONV_TILE = 16;  // forward / input-gradient output tile edge
+constexpr int WG_TH = 8;       // rows of a weight-gradient tile (16 columns)
+enum { IN_VLAM = 0, IN_BF16 = 1 };
+enum { OUT_RELU_BF16 = 0, OUT_F32_PLANAR = 1, OUT_MASK_BF16 = 2 };
+
+struct ConvArgs {
+    int n = 0, H = 0, W = 0;
+    const float* v = nullptr;       // IN_VLAM: [n][H][W]
+    const float* lam = nullptr;     // [n] (device)
+    const uint16_t* in = nullptr;   // IN_BF16: [n][H][W][cin] bf16
+    const uint16_t* in_lo = nullptr;// split: low parts of in
+    const uint16_t* wt = nullptr;   // [coutp][kp] bf16
+    const uint16_t* wt_lo = nullptr;// split: low parts of wt
+    const float* bias = nullptr;    // forward: [cout]
+    uint16_t* out_bf = nullptr;     // [n][H][W][32] bf16
+    uint16_t* out_lo = nullptr;     // split OUT_RELU_BF16: low parts
+    const uint16_t* mask = nullptr; // OUT_MASK_BF16: keep where mask > 0
+    float* out_f = nullptr;         // OUT_F32_PLANAR: [n][2][H][W]
+    int proj = 0;                   // OUT_F32_PLANAR: project onto the lam ball
+    int tiles_x = 0, tiles_y = 0, n_tiles = 0;
+};
+struct WgradArgs {
+    int n = 0, H = 0, W = 0;
+    const float* v = nullptr;       // IN_VLAM input
+    const float* lam = nullptr;
+    const uint16_t* x = nullptr;    // IN_BF16 input [n][H][W][cin]
+    const uint16_t* g = nullptr;    // output gradient [n][H][W][cout]
+    float* part = nullptr;          // [blocks][(9 cin + 1) cout]
+    int tiles_x = 0, tiles_y = 0, n_tiles = 0;
+};
+struct HeadArgs {
+    int n = 0, H = 0, W = 0, nonneg = 0;
+    const float* qt = nullptr;      // [n][2][H][W]
+    const float* v = nullptr;       // [n][H][W]
+    const float* lam = nullptr;     // [n]
+    float* z = nullptr;             // nullable
+    const float* z_target = nullptr;// training only
+    float* gu = nullptr;            // training: dL/du [n][H][W]
+    float inv_npx = 0.f;
+    double* loss_part = nullptr;    // [blocks]
+    double* loss_out = nullptr;     // sum of squared errors
+    uint16_t* gq_bf = nullptr;      // backward: [n][H][W][2] bf16
+};
+void launch_conv(tvs_ctx* ctx, int cin, int coutp, int in_mode, int out_mode, bool split,
+                 ConvArgs a);
+int wgrad_blocks(const tvs_ctx* ctx, int n, int H, int W);
+void launch_wgrad(tvs_ctx* ctx, int layer, WgradArgs a, float* grad_out);
+int head_blocks(const tvs_ctx* ctx, size_t tot);
+void launch_head_fwd(tvs_ctx* ctx, HeadArgs a, int nblk);
+void launch_head_bwd(tvs_ctx* ctx, HeadArgs a, int nblk);
+void launch_adam(tvs_ctx* ctx, int n, float* p, const float* grad, float* m, float* v, float lr,
+                 float b1, float b2, float c1, float c2, float eps);
+void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, uint16_t* wf_lo,
+                 uint16_t* wb);
+}  // namespace cnn
+
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace tvs

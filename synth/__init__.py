@@ -209,3 +209,33 @@ def batched_slice_inputs(sl: dict):
     """Phantom and noise field of one batched slice (float64)."""
     return phantom_and_noise(sl["H"], sl["W"], sl["n_ellipses"], sl["seed"],
                              (sl["H"], sl["W"]))
+
+
+# ---------------------------------------------------------------- learned prox
+CNN_LAYERS = ((2, 32), (32, 32), (32, 32), (32, 2))  # (in, out) channels, 3x3 kernels
+
+
+def cnn_params(seed: int, scale: float = 1.0, bias_sd: float = 0.05) -> np.ndarray:
+    """Seeded parameter vector of the learned-prox network (per layer
+    W[9][in][out] then b[out]): He-scaled normal weights, small normal biases."""
+    rng = _rng(seed)
+    parts = []
+    for ci, co in CNN_LAYERS:
+        parts.append(rng.standard_normal(9 * ci * co) * scale * np.sqrt(2.0 / (9 * ci)))
+        parts.append(rng.standard_normal(co) * bias_sd)
+    return np.concatenate(parts)
+
+
+def prox_training_inputs(n: int, H: int, W: int, seed: int, sigma=(0.02, 0.15),
+                         lam=(0.02, 1.0), n_ellipses=(10, 30)):
+    """n noisy phantoms v = u + sigma * noise and their prox weights lam
+    (log-uniform), the inputs of the learned prox's training pairs."""
+    rng = _rng(seed)
+    vs = np.empty((n, H, W))
+    lams = np.exp(rng.uniform(np.log(lam[0]), np.log(lam[1]), n))
+    for k in range(n):
+        s = int(rng.integers(0, 2**31 - 1))
+        ne = int(rng.integers(n_ellipses[0], n_ellipses[1] + 1))
+        u, eta = phantom_and_noise(H, W, ne, s, (H, W))
+        vs[k] = u + rng.uniform(sigma[0], sigma[1]) * eta
+    return vs, lams

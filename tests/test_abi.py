@@ -77,3 +77,12 @@ def test_solver_parameter_validation_messages():
     st = _lib.tvs_state()
     rc = L.tvs_proxskip(None, 0, None, C.byref(st), C.byref(P), None, None, None)
     assert rc == 1
+
+
+def test_learned_prox_parameter_count_and_null_checks():
+    assert T.tvs_cnn_param_count() == O.cnn_param_count() == 19682
+    L = _lib.lib()
+    out = C.c_void_p()
+    assert L.tvs_cnn_create(None, 0, C.byref(out)) == 1
+    assert L.tvs_cnn_forward(None, 1, 4, 4, None, None, 0, None, None) == 1
+    assert L.tvs_cnn_prox(None, 4, 4, None, 0.1, 0, 1e-3, 10, None, None, None, None) == 1

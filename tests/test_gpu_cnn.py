@@ -1,0 +1,198 @@
+"""GPU parity of the learned TV prox against the FP64 oracle.
+
+The network runs on BF16 matrix cores with FP32 accumulation (8 significand
+bits per operand), so the bar is the one for BF16 work: relative L2 error
+<= 2e-2 and cosine >= 0.999 against the oracle on the same parameters and
+inputs.  Adam runs in FP32 and is held to 1e-5.  The gate and fallback of the
+gap-gated prox are compared bitwise with the FGP prox they call.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2411_00688_amd as T
+import synth
+from gpu_util import F32, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+LAYER_SIZES = [9 * ci * co + co for ci, co in synth.CNN_LAYERS]
+
+
+def cosine(a, b):
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def inputs(n, H, W, seed, nonneg=0):
+    v, lam = synth.prox_training_inputs(n, H, W, seed, lam=(0.05, 0.6))
+    if nonneg:
+        v = v - 0.15
+    return synth.to_f32_exact(v), lam
+
+
+@pytest.fixture
+def cnn(ctx):
+    c = T.tvs_cnn_create(ctx, 5)
+    yield c
+    T.tvs_cnn_destroy(c)
+
+
+def set_params(cnn, seed, scale=1.0):
+    P = synth.to_f32_exact(synth.cnn_params(seed, scale))
+    T.tvs_cnn_set_params(cnn, P)
+    return P
+
+
+# Two-part operands (default): products to about 2^-16, FP32 accumulation
+# over K <= 288 terms; four layers compound that to ~1e-4.  Single-part BF16
+# (fast): 2^-9 per operand, ~1e-2 after four layers.
+FWD_TOL = {False: 1e-3, True: 2e-2}
+
+
+@pytest.mark.parametrize("fast", [False, True])
+@pytest.mark.parametrize("n,H,W,nonneg", [(3, 37, 45, 0), (2, 33, 16, 1), (1, 1, 50, 0),
+                                          (2, 50, 1, 1), (1, 16, 16, 0)])
+def test_forward_matches_oracle(cnn, n, H, W, nonneg, fast):
+    P = set_params(cnn, 100 + H)
+    T.tvs_cnn_set_fast_forward(cnn, fast)
+    v, lam = inputs(n, H, W, 200 + W, nonneg)
+    qt = torch.empty(n, 2, H, W, dtype=F32, device="cuda")
+    z = torch.empty(n, H, W, dtype=F32, device="cuda")
+    T.tvs_cnn_forward(cnn, dev(v, F32), lam, nonneg, qt, z)
+    qt_ref, z_ref = O.cnn_forward(v, lam, P, nonneg)
+    tol = FWD_TOL[fast]
+    e_qt, e_z = rel_l2(host(qt), qt_ref), rel_l2(host(z), z_ref)
+    print(f"fast={fast} qt rel {e_qt:.2e} z rel {e_z:.2e}")
+    assert e_qt < tol and e_z < tol
+    assert cosine(host(qt).ravel(), qt_ref.ravel()) > 0.999
+    # z = v + div P_lam(qt): its deviation is at most a few times that of qt
+    assert np.abs(host(z) - z_ref).max() < 4 * tol * np.abs(qt_ref).max() + 1e-6
+
+
+def test_forward_sampled_at_512(cnn):
+    """A 512 x 512 image (the CT workload's size) in one launch per layer;
+    sampled rows against the oracle run on a band of rows around them (the
+    network sees 4 pixels on each side, so rows i-4 .. i+4 determine row i)."""
+    P = set_params(cnn, 7)
+    v, lam = inputs(1, 512, 512, 9)
+    qt = torch.empty(1, 2, 512, 512, dtype=F32, device="cuda")
+    T.tvs_cnn_forward(cnn, dev(v, F32), lam, 0, qt, None)
+    got = host(qt)[0]
+    for r in (0, 3, 200, 508, 511):
+        lo, hi = max(r - 4, 0), min(r + 5, 512)
+        band = v[0][lo:hi]
+        qt_ref, _ = O.cnn_forward(band[None], lam, P, 0)
+        row_ref = qt_ref[0][:, r - lo]
+        assert rel_l2(got[:, r], row_ref) < FWD_TOL[False], r
+
+
+@pytest.mark.parametrize("nonneg", [0, 1])
+def test_gradient_matches_oracle(cnn, nonneg):
+    P = set_params(cnn, 300 + nonneg)
+    n, H, W = 3, 29, 40
+    v, lam = inputs(n, H, W, 400 + nonneg, nonneg)
+    _, zt = O.cnn_forward(v, lam, synth.cnn_params(999, 0.5), nonneg)
+    zt = synth.to_f32_exact(zt)
+    grad = torch.empty(T.tvs_cnn_param_count(), dtype=F32, device="cuda")
+    loss = T.tvs_cnn_loss_grad(cnn, dev(v, F32), lam, dev(zt, F32), nonneg, grad)
+    loss_ref, g_ref = O.cnn_loss_grad(v, lam, P, zt, nonneg)
+    g = host(grad)
+    print(f"loss rel {abs(loss - loss_ref) / loss_ref:.2e} grad rel {rel_l2(g, g_ref):.2e} "
+          f"cos {cosine(g, g_ref):.6f}")
+    assert abs(loss - loss_ref) <= 1e-3 * loss_ref
+    assert rel_l2(g, g_ref) < 2e-2
+    assert cosine(g, g_ref) > 0.999
+    o = 0
+    for k, sz in enumerate(LAYER_SIZES):
+        assert rel_l2(g[o:o + sz], g_ref[o:o + sz]) < 3e-2, k
+        o += sz
+
+
+def test_adam_matches_oracle(cnn):
+    P = set_params(cnn, 12)
+    rng = np.random.default_rng(13)
+    m, vv, p64 = np.zeros(P.size), np.zeros(P.size), P.astype(np.float64)
+    for k in range(1, 4):
+        g = synth.to_f32_exact(rng.standard_normal(P.size) * 10.0 ** rng.uniform(-4, 0, P.size))
+        T.tvs_cnn_adam_step(cnn, 1e-2, dev(g, F32))
+        O.adam_step(p64, g, m, vv, k, 1e-2)
+    got = T.tvs_cnn_get_params(cnn).astype(np.float64)
+    assert np.abs(got - p64).max() < 1e-5 * max(1.0, np.abs(p64).max())
+
+
+def test_training_reduces_loss(cnn):
+    """Adam on a fixed batch of prox pairs (targets from the oracle's FGP)."""
+    set_params(cnn, 41)
+    n, H, W = 4, 48, 48
+    v, lam = inputs(n, H, W, 77)
+    zt = np.stack([O.fgp(v[k], lam[k], 300)[0] for k in range(n)])
+    zt = synth.to_f32_exact(zt)
+    vd, zd = dev(v, F32), dev(zt, F32)
+    first = T.tvs_cnn_loss_grad(cnn, vd, lam, zd)
+    for _ in range(60):
+        T.tvs_cnn_train_step(cnn, vd, lam, zd, 2e-3, want_loss=False)
+    last = T.tvs_cnn_loss_grad(cnn, vd, lam, zd)
+    assert last < 0.5 * first, (first, last)
+
+
+def test_gated_prox_gate_and_fallback(cnn, ctx):
+    set_params(cnn, 21, 0.5)
+    H, W = 40, 52
+    v, lam = inputs(1, H, W, 22)
+    v, lam = v[0], float(lam[0])
+    vd = dev(v, F32)
+    q = torch.empty(2, H, W, dtype=F32, device="cuda")
+    z = torch.empty(H, W, dtype=F32, device="cuda")
+    # gate open: the network's projected dual and its primal point
+    fb, rg = T.tvs_cnn_prox(cnn, vd, lam, 0, float("inf"), 25, q, z)
+    assert not fb
+    qt = torch.empty(1, 2, H, W, dtype=F32, device="cuda")
+    z_net = torch.empty(1, H, W, dtype=F32, device="cuda")
+    T.tvs_cnn_forward(cnn, vd, lam, 0, qt, z_net)
+    q_proj = host(q)
+    assert np.all(np.hypot(q_proj[0], q_proj[1]) <= lam * (1 + 1e-6))
+    assert np.abs(host(z) - host(z_net)[0]).max() < 1e-5
+    gap, primal = T.tvs_tv_gap(ctx, vd, lam, 0, q)
+    assert abs(rg - gap / primal) <= 1e-12 + 1e-9 * abs(rg)
+    # gate closed: FGP warm-started from the network's dual, bitwise
+    q2 = torch.empty_like(q)
+    z2 = torch.empty_like(z)
+    fb, rg2 = T.tvs_cnn_prox(cnn, vd, lam, 0, 0.0, 25, q2, z2)
+    assert fb and rg2 == rg
+    q3 = q.clone()
+    z3 = torch.empty_like(z)
+    T.tvs_tv_prox(ctx, vd, lam, 25, 0, q3, z3)
+    assert torch.equal(q2, q3) and torch.equal(z2, z3)
+
+
+def test_save_load_roundtrip(cnn, ctx, tmp_path):
+    P = set_params(cnn, 31)
+    path = os.path.join(tmp_path, "net.bin")
+    T.tvs_cnn_save(cnn, path)
+    other = T.tvs_cnn_create(ctx, 99)
+    try:
+        assert not np.array_equal(T.tvs_cnn_get_params(other), P)
+        T.tvs_cnn_load(other, path)
+        assert np.array_equal(T.tvs_cnn_get_params(other), P)
+    finally:
+        T.tvs_cnn_destroy(other)
+    with open(path, "r+b") as f:
+        f.seek(8)
+        f.write(np.int64(5).tobytes())
+    with pytest.raises(T.TvsError):
+        T.tvs_cnn_load(cnn, path)
+
+
+def test_create_is_seeded(ctx):
+    a, b, c = (T.tvs_cnn_create(ctx, s) for s in (1, 1, 2))
+    try:
+        pa, pb, pc = (T.tvs_cnn_get_params(x) for x in (a, b, c))
+        assert np.array_equal(pa, pb) and not np.array_equal(pa, pc)
+        w1 = pa[:9 * 2 * 32]
+        assert abs(w1.std() - np.sqrt(2.0 / 18)) < 0.1 * np.sqrt(2.0 / 18)
+    finally:
+        for x in (a, b, c):
+            T.tvs_cnn_destroy(x)
