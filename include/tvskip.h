@@ -336,9 +336,40 @@ tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
 tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, int nonneg,
                         double gap_tol, int fallback_iters, float* q_out, float* z_out,
                         int* fell_back_out, double* rel_gap_out);
+/* ------------------------------------------- solver runs with extensions
+ * tvs_proxskip / tvs_pdhgskip with two optional parts, set in a
+ * tvs_solve_ext (NULL: the plain call):
+ *  - cnn != NULL: every prox call of the run is the learned prox with the
+ *    duality-gap gate of tvs_cnn_prox, decided on the device (so the run
+ *    stays one HIP graph with TVS_FLAG_GRAPH): q <- P_lam(qt) from the
+ *    network; if its relative gap exceeds gap_tol, params->inner_iters FGP
+ *    iterations warm-started from it.  The network's dual replaces the warm
+ *    dual of the previous call.  float32 only (TVS_ERR_UNSUPPORTED else).
+ *  - v_record != NULL: the prox inputs v (the argument of the prox in
+ *    Alg. "ProxSkip" / "PDHGSkip-2") of the first max_record prox calls are
+ *    copied to v_record (device, dtype, max_record x H x W), the pairs that
+ *    train the network.
+ * Outputs: n_fallback = calls where FGP ran, n_recorded = inputs stored. */
+typedef struct tvs_solve_ext {
+    tvs_cnn* cnn;
+    double gap_tol;
+    void* v_record;
+    int64_t max_record;
+    int64_t n_fallback;   /* out */
+    int64_t n_recorded;   /* out */
+} tvs_solve_ext;
+
+tvs_status tvs_proxskip_ex(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                           const tvs_params* params, tvs_solve_ext* ext, double* obj_trace,
+                           uint8_t* theta_trace, tvs_report* report);
+tvs_status tvs_pdhgskip_ex(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                           const tvs_params* params, tvs_solve_ext* ext, double* obj_trace,
+                           uint8_t* theta_trace, tvs_report* report);
+
 /* fast != 0: tvs_cnn_forward and tvs_cnn_prox use single-part BF16
  * operands (one product per K slice, about three times fewer matrix-core
- * operations, BF16-level error); 0 (the default): two-part operands. */
+ * operations, BF16-level error); 0 (the default): two-part operands.  Also
+ * applies to the learned prox inside tvs_proxskip_ex / tvs_pdhgskip_ex. */
 tvs_status tvs_cnn_set_fast_forward(tvs_cnn* cnn, int fast);
 /* Save / load the parameters as a little-endian binary file: the 8 bytes
  * "TVSCNN01", an int64 parameter count, then the float32 parameters.

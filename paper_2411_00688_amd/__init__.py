@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes as C
 
 from ._lib import (TVS_F32, TVS_F64, TVS_FLAG_GRAPH, TvsError, check, lib, tvs_batch_params,
-                   tvs_params, tvs_report, tvs_slice, tvs_state)
+                   tvs_params, tvs_report, tvs_slice, tvs_solve_ext, tvs_state)
 
 __all__ = [
     "TVS_F32", "TVS_F64", "TVS_FLAG_GRAPH", "TvsError",
@@ -21,7 +21,7 @@ __all__ = [
     "tvs_op_identity", "tvs_op_blur_periodic", "tvs_op_ct_joseph", "tvs_op_destroy",
     "tvs_op_out_size", "tvs_op_apply", "tvs_op_adjoint", "tvs_op_norm",
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
-    "tvs_proxskip", "tvs_pdhgskip",
+    "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
     "tvs_proxskip_batched", "tvs_fgp_set_variant_batched",
     "tvs_cnn_create", "tvs_cnn_destroy", "tvs_cnn_param_count", "tvs_cnn_get_params",
@@ -195,7 +195,7 @@ def tvs_coin(seed: int, stream_id: int, k: int, p: float) -> int:
 
 # ---------------------------------------------------------------- solvers
 def _solve(fn, op, b, x, h, q, y, alpha, step, dual_step, p, outer_iters, inner_iters, nonneg,
-           seed, stream_id, k0, graph, want_obj, want_theta):
+           seed, stream_id, k0, graph, want_obj, want_theta, ext=None):
     import numpy as np
     d = _dtype_code(x)
     n = x.numel()
@@ -208,12 +208,27 @@ def _solve(fn, op, b, x, h, q, y, alpha, step, dual_step, p, outer_iters, inner_
     rep = tvs_report()
     obj = np.zeros(max(int(outer_iters), 1)) if want_obj else None
     th = np.zeros(max(int(outer_iters), 1), dtype=np.uint8) if want_theta else None
-    check(fn(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st), C.byref(P),
-             obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
+    args = [C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st), C.byref(P)]
+    if ext is not None:
+        args.append(C.byref(ext))
+    check(fn(*args, obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
              th.ctypes.data_as(C.POINTER(C.c_uint8)) if want_theta else None, C.byref(rep)))
-    return dict(n_prox=rep.n_prox, iters=rep.iters,
-                obj=obj[:outer_iters] if want_obj else None,
-                theta=th[:outer_iters] if want_theta else None)
+    out = dict(n_prox=rep.n_prox, iters=rep.iters,
+               obj=obj[:outer_iters] if want_obj else None,
+               theta=th[:outer_iters] if want_theta else None)
+    if ext is not None:
+        out.update(n_fallback=ext.n_fallback, n_recorded=ext.n_recorded)
+    return out
+
+
+def _ext(cnn, gap_tol, v_record):
+    e = tvs_solve_ext()
+    e.cnn = C.c_void_p(cnn) if cnn else None
+    e.gap_tol = float(gap_tol)
+    if v_record is not None:
+        e.v_record = _ptr(v_record)
+        e.max_record = int(v_record.shape[0])
+    return e
 
 
 def tvs_proxskip(op: int, b, x, h, q, alpha, step, p, outer_iters, inner_iters, nonneg=0,
@@ -229,6 +244,24 @@ def tvs_pdhgskip(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inne
     """PDHGSkip-2 in place on (x, h, q, y).  Returns dict(n_prox, iters, obj, theta)."""
     return _solve(lib().tvs_pdhgskip, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
                   inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta)
+
+
+def tvs_proxskip_ex(op: int, b, x, h, q, alpha, step, p, outer_iters, inner_iters, nonneg=0,
+                    seed=0, stream_id=0, k0=0, graph=False, want_obj=False, want_theta=False,
+                    cnn=None, gap_tol=1e-3, v_record=None):
+    """tvs_proxskip with the learned prox (cnn) and / or prox-input recording
+    (v_record: (max_record, H, W) tensor).  Adds n_fallback, n_recorded."""
+    return _solve(lib().tvs_proxskip_ex, op, b, x, h, q, None, alpha, step, 0.0, p, outer_iters,
+                  inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta,
+                  ext=_ext(cnn, gap_tol, v_record))
+
+
+def tvs_pdhgskip_ex(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inner_iters,
+                    nonneg=0, seed=0, stream_id=0, k0=0, graph=False, want_obj=False,
+                    want_theta=False, cnn=None, gap_tol=1e-3, v_record=None):
+    return _solve(lib().tvs_pdhgskip_ex, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
+                  inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta,
+                  ext=_ext(cnn, gap_tol, v_record))
 
 
 # ------------------------------------------------------------- FGP tuning

@@ -590,7 +590,8 @@ static void check_params(const tvs_params* P, bool pdhg) {
 // device array receiving Phi(x_{k+1}).
 template <typename T>
 static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
-                       const tvs_params* P, const std::vector<uint8_t>& theta, double* obj_dev) {
+                       const tvs_params* P, const std::vector<uint8_t>& theta, double* obj_dev,
+                       const SolveExt& ext) {
     tvs_ctx* ctx = op->ctx;
     const int H = op->H, W = op->W;
     const size_t n = (size_t)H * W, m = op->out_size();
@@ -637,6 +638,7 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
     ps.step = (T)step;
     ps.coef = (T)(step - step / p);
     ps.pdhg = pdhg ? 1 : 0;
+    int64_t call = 0;
     for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
         ps.theta = theta[kk];
         // data-fidelity step, fused with the control-variate bookkeeping
@@ -661,7 +663,17 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
         }
         // the prox, only when the coin says so
         if (ps.theta) {
-            T* qf = run_fgp<T>(ctx, H, W, v, lam, P->inner_iters, P->nonneg, q, cfg);
+            if (ext.v_record && call < ext.max_record)
+                launch_copy<T>(ctx, n, v, (T*)ext.v_record + (size_t)call * n);
+            T* qf;
+            if (ext.cnn) {
+                qf = (T*)cnn::enqueue_solver_prox(ext.cnn, H, W, (const float*)v, lam, P->nonneg,
+                                                  ext.gap_tol, P->inner_iters, (float*)q, cfg,
+                                                  ext.gate + call);
+            } else {
+                qf = run_fgp<T>(ctx, H, W, v, lam, P->inner_iters, P->nonneg, q, cfg);
+            }
+            ++call;
             Finalize<T> f{};
             f.v = v;
             f.q = qf;
@@ -717,7 +729,7 @@ static void prepare_solver(tvs_op* op, bool pdhg, const tvs_params* P) {
 
 static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* st,
                         const tvs_params* P, double* obj_trace, uint8_t* theta_trace,
-                        tvs_report* report, bool pdhg) {
+                        tvs_report* report, bool pdhg, tvs_solve_ext* ext_io) {
     return guarded([&] {
         TVS_REQUIRE(op && b && st, TVS_ERR_INVALID_ARG, "null pointer");
         check_dtype(dtype);
@@ -736,20 +748,56 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
         double* obj_dev = nullptr;
         if (obj_trace && K > 0) obj_dev = (double*)scratch(ctx, S_OBJ, (size_t)K * sizeof(double));
         const bool use_graph = (P->flags & TVS_FLAG_GRAPH) && !obj_dev && K > 0;
+        SolveExt ext;
+        if (ext_io) {
+            TVS_REQUIRE(ext_io->max_record >= 0 && (ext_io->v_record || ext_io->max_record == 0),
+                        TVS_ERR_INVALID_ARG, "v_record required when max_record > 0");
+            ext.v_record = ext_io->v_record;
+            ext.max_record = ext_io->max_record;
+            if (ext_io->cnn) {
+                TVS_REQUIRE(dtype == TVS_F32, TVS_ERR_UNSUPPORTED,
+                            "the learned prox runs on float32 only");
+                TVS_REQUIRE(!std::isnan(ext_io->gap_tol), TVS_ERR_INVALID_ARG,
+                            "gap_tol must be a number");
+                ext.cnn = ext_io->cnn;
+                ext.gap_tol = ext_io->gap_tol;
+                ext.gate = (int*)scratch(ctx, S_GATE, (size_t)(nprox > 0 ? nprox : 1) * sizeof(int));
+                cnn::prepare_solver_prox(ext.cnn, op->H, op->W, P->alpha * P->step / P->p);
+            }
+        }
         if (dtype == TVS_F32)
             prepare_solver<float>(op, pdhg, P);
         else
             prepare_solver<double>(op, pdhg, P);
         auto enqueue = [&] {
             if (dtype == TVS_F32)
-                run_solver<float>(op, pdhg, (const float*)b, st, P, theta, obj_dev);
+                run_solver<float>(op, pdhg, (const float*)b, st, P, theta, obj_dev, ext);
             else
-                run_solver<double>(op, pdhg, (const double*)b, st, P, theta, obj_dev);
+                run_solver<double>(op, pdhg, (const double*)b, st, P, theta, obj_dev, ext);
         };
-        if (use_graph)
-            graph_run(ctx, op, pdhg, (int)dtype, b, st, P, enqueue);
-        else
+        if (use_graph) {
+            std::vector<uint64_t> key = graph_key(op, pdhg, (int)dtype, b, st, P);
+            uint64_t tol_bits;
+            std::memcpy(&tol_bits, &ext.gap_tol, sizeof(tol_bits));
+            key.insert(key.end(), {(uint64_t)(uintptr_t)ext.cnn, tol_bits,
+                                   (uint64_t)(uintptr_t)ext.v_record, (uint64_t)ext.max_record,
+                                   (uint64_t)(uintptr_t)ext.gate,
+                                   ext.cnn ? (uint64_t)cnn::fast_forward(ext.cnn) : 0});
+            graph_run_key(ctx, key, enqueue);
+        } else {
             enqueue();
+        }
+        if (ext_io) {
+            ext_io->n_recorded = nprox < ext.max_record ? nprox : ext.max_record;
+            ext_io->n_fallback = 0;
+            if (ext.cnn && nprox > 0) {
+                std::vector<int> g((size_t)nprox);
+                TVS_HIP(hipMemcpyAsync(g.data(), ext.gate, (size_t)nprox * sizeof(int),
+                                       hipMemcpyDeviceToHost, ctx->stream));
+                TVS_HIP(hipStreamSynchronize(ctx->stream));
+                for (int v : g) ext_io->n_fallback += v;
+            }
+        }
         if (theta_trace && K > 0) std::memcpy(theta_trace, theta.data(), (size_t)K);
         if (obj_dev) {
             TVS_HIP(hipMemcpyAsync(obj_trace, obj_dev, (size_t)K * sizeof(double),
@@ -768,11 +816,25 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
 extern "C" tvs_status tvs_proxskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
                                    const tvs_params* params, double* obj_trace,
                                    uint8_t* theta_trace, tvs_report* report) {
-    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, false);
+    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, false, nullptr);
 }
 
 extern "C" tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
                                    const tvs_params* params, double* obj_trace,
                                    uint8_t* theta_trace, tvs_report* report) {
-    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, true);
+    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, true, nullptr);
+}
+
+extern "C" tvs_status tvs_proxskip_ex(tvs_op* op, tvs_dtype dtype, const void* b,
+                                      tvs_state* state, const tvs_params* params,
+                                      tvs_solve_ext* ext, double* obj_trace,
+                                      uint8_t* theta_trace, tvs_report* report) {
+    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, false, ext);
+}
+
+extern "C" tvs_status tvs_pdhgskip_ex(tvs_op* op, tvs_dtype dtype, const void* b,
+                                      tvs_state* state, const tvs_params* params,
+                                      tvs_solve_ext* ext, double* obj_trace,
+                                      uint8_t* theta_trace, tvs_report* report) {
+    return solve(op, dtype, b, state, params, obj_trace, theta_trace, report, true, ext);
 }

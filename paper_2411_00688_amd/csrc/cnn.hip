@@ -303,6 +303,45 @@ static void destroy(tvs_cnn* c) {
     delete c;
 }
 
+bool fast_forward(const tvs_cnn* c) { return c->fast; }
+
+void prepare_solver_prox(tvs_cnn* c, int H, int W, double lam) {
+    TVS_REQUIRE(c && c->ctx, TVS_ERR_INVALID_ARG, "null network");
+    check_batch(1, H, W);
+    const size_t npx = (size_t)H * W;
+    set_lam(c, 1, &lam);
+    for (int l = 0; l < 3; ++l) {
+        grow(c, tvs_cnn::B_X1 + l, npx * 64);
+        if (!c->fast) grow(c, tvs_cnn::B_X1L + l, npx * 64);
+    }
+    scratch(c->ctx, S_Z, npx * sizeof(float));
+    reserve_reduce_scratch(c->ctx, npx);
+}
+
+float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam, int nonneg,
+                           double tol, int iters, float* q, const FgpConfig& cfg, int* record) {
+    tvs_ctx* ctx = c->ctx;
+    const size_t npx = (size_t)H * W;
+    forward_convs(c, 1, H, W, v, q, 1, !c->fast);  // q <- P_lam(qt)
+    // relative duality gap of the network's dual (the standalone gap path)
+    float* z = (float*)scratch(ctx, S_Z, npx * sizeof(float));
+    Finalize<float> f{};
+    f.v = v;
+    f.q = q;
+    f.q_out = q;
+    f.z = z;
+    f.nonneg = nonneg;
+    f.mode = 0;
+    launch_finalize<float>(ctx, H, W, f);
+    double* red = (double*)scratch(ctx, S_RED, 8 * sizeof(double));
+    reduce_gap<float>(ctx, H, W, v, z, q, lam, red + 0, red + 1);
+    int* flag = record;  // the per-call record doubles as this call's flag
+    launch_gate(ctx, red, tol, flag, nullptr);
+    float* qf = run_fgp<float>(ctx, H, W, v, lam, iters, nonneg, q, cfg, flag);
+    if (qf != q) launch_copy_if_off(ctx, 2 * npx, flag, q, qf);
+    return qf;
+}
+
 }  // namespace cnn
 }  // namespace tvs
 

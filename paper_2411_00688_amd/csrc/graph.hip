@@ -20,7 +20,7 @@ static uint64_t bits(double d) {
     return u;
 }
 
-static std::vector<uint64_t> make_key(const tvs_op* op, bool pdhg, int dtype, const void* b,
+std::vector<uint64_t> graph_key(const tvs_op* op, bool pdhg, int dtype, const void* b,
                                       const tvs_state* st, const tvs_params* P) {
     return {(uint64_t)(uintptr_t)op, (uint64_t)pdhg, (uint64_t)dtype, (uint64_t)(uintptr_t)b,
             (uint64_t)(uintptr_t)st->x, (uint64_t)(uintptr_t)st->h, (uint64_t)(uintptr_t)st->q,
@@ -42,7 +42,7 @@ void graph_cache_clear(tvs_ctx* ctx) {
 
 void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void* b,
                const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue) {
-    graph_run_key(ctx, make_key(op, pdhg, dtype, b, st, P), enqueue);
+    graph_run_key(ctx, graph_key(op, pdhg, dtype, b, st, P), enqueue);
 }
 
 void graph_run_key(tvs_ctx* ctx, const std::vector<uint64_t>& key,

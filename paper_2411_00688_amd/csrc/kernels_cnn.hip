@@ -481,6 +481,28 @@ __global__ void pack_weights_kernel(const float* w, int cin, int cout, int coutp
     }
 }
 
+// ------------------------------------------------------------------ gate
+// flag = [relative duality gap > tol], from the two sums of the gap
+// reduction (gap, primal value); record (nullable) keeps the decision.
+__global__ void gate_kernel(const double* red, double tol, int* flag, int* record) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double gap = red[0], primal = red[1];
+        const double rel = primal > 0.0 ? gap / primal : gap;
+        const int f = rel > tol ? 1 : 0;
+        flag[0] = f;
+        if (record) record[0] = f;
+    }
+}
+
+// dst = src where the gate is off (FGP did not run, so its output buffer
+// must receive the network's dual)
+__global__ void copy_if_off_kernel(size_t n, const int* flag, const float* src, float* dst) {
+    if (*flag != 0) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------ launchers
 static int grid_for(const tvs_ctx* ctx, int tiles, int per_cu) {
     int g = ctx->n_cu * per_cu;
@@ -590,6 +612,18 @@ void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, 
     const int tot = coutp * kp + (wb ? 32 * kpb : 0);
     pack_weights_kernel<<<div_up(tot, 256), 256, 0, ctx->stream>>>(w, cin, cout, coutp, kp, wf,
                                                                     wf_lo, kpb, wb);
+    TVS_LAUNCH_CHECK();
+}
+
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* record) {
+    gate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, flag, record);
+    TVS_LAUNCH_CHECK();
+}
+
+void launch_copy_if_off(tvs_ctx* ctx, size_t n, const int* flag, const float* src, float* dst) {
+    size_t b = (n + 255) / 256;
+    const size_t cap = (size_t)ctx->n_cu * 8;
+    copy_if_off_kernel<<<(int)(b < cap ? b : cap), 256, 0, ctx->stream>>>(n, flag, src, dst);
     TVS_LAUNCH_CHECK();
 }
 

@@ -56,6 +56,7 @@ struct FgpArgs {
     int nonneg;
     int H, W;
     size_t plane;  // H * W
+    const int* run_flag = nullptr;  // if set and *run_flag == 0 the launch does nothing
 };
 
 // bit flags of a pixel's neighbour relations, precomputed once per launch
@@ -185,6 +186,7 @@ __device__ __forceinline__ void fgp_tile(const FgpArgs<T>& a, int ty, int tx) {
 
 template <typename T, int BW, int BH, int TS>
 __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
+    if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
     fgp_tile<T, BW, BH, TS>(a, (int)blockIdx.y, (int)blockIdx.x);
 }
 
@@ -284,7 +286,7 @@ static int find_variant(const FgpConfig& c, int dtype_bytes) {
 // (q_inout itself or a scratch buffer).  q_inout is only read.
 template <typename T>
 T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
-           T* q_inout, const FgpConfig& cfg) {
+           T* q_inout, const FgpConfig& cfg, const int* run_flag) {
     const size_t plane = (size_t)H * W;
     const int vi = find_variant(cfg, (int)sizeof(T));
     const int TS = kFgpVariants[vi].ts;
@@ -315,6 +317,7 @@ T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int
         a.H = H;
         a.W = W;
         a.plane = plane;
+        a.run_flag = run_flag;
         launch_fgp_variant<T>(vi, a, ctx->stream);
         TVS_LAUNCH_CHECK();
         if (ns > 1) {
@@ -549,7 +552,8 @@ void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T* u) {
 }
 
 #define TVS_INST(T)                                                                          \
-    template T* run_fgp<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, const FgpConfig&); \
+    template T* run_fgp<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, const FgpConfig&,  \
+                           const int*);                                                         \
     template T* run_fgp_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&, const T*, T*,   \
                                    size_t, int, int, const FgpConfig&);                          \
     template void launch_finalize_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&,      \

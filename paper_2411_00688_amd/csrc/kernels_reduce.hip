@@ -35,6 +35,11 @@ __device__ __forceinline__ double block_sum(double v, double* s_w) {
 
 static int nblocks(size_t n) { return (int)((n + RCHUNK - 1) / RCHUNK); }
 
+void reserve_reduce_scratch(tvs_ctx* ctx, size_t n) {
+    scratch(ctx, S_PART, (size_t)3 * nblocks(n) * sizeof(double));
+    scratch(ctx, S_RED, 8 * sizeof(double));
+}
+
 // sum (a - b)^2, or sum a^2 if b is null
 template <typename T>
 __global__ __launch_bounds__(RB) void sqdiff_stage1(size_t n, const T* a, const T* b, double* part) {

@@ -51,7 +51,7 @@ struct Scratch {
 enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
     S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
-    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_COUNT
+    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_COUNT
 };
 
 struct GraphEntry;
@@ -186,7 +186,7 @@ int fgp_variant_count();
 FgpConfig fgp_variant(int index);
 template <typename T>
 T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
-           T* q_inout, const FgpConfig& cfg);
+           T* q_inout, const FgpConfig& cfg, const int* run_flag = nullptr);
 
 // z = P_X(v + div q) and the ProxSkip / PDHGSkip bookkeeping after a prox.
 template <typename T>
@@ -259,6 +259,9 @@ double* reduce_tv(tvs_ctx* ctx, int H, int W, const T* u, double* out_dev);
 template <typename T>
 void reduce_gap(tvs_ctx* ctx, int H, int W, const T* v, const T* z, const T* q, double lam,
                 double* gap_dev, double* primal_dev);
+// grows the reduction scratch so that the reductions over n elements can
+// later be enqueued during graph capture
+void reserve_reduce_scratch(tvs_ctx* ctx, size_t n);
 template <typename T>
 double* reduce_dot(tvs_ctx* ctx, size_t n, const T* a, const T* b, double* out_dev);
 // out[0] = a*x[0] + b*y[0] on the device (scalars combined in float64)
@@ -294,6 +297,8 @@ void launch_identity_step_batched(tvs_ctx* ctx, const BSlice<T>* sl, const int* 
 // ctx->stream.  All scratch memory must already be allocated.
 void graph_run(tvs_ctx* ctx, const tvs_op* op, bool pdhg, int dtype, const void* b,
                const tvs_state* st, const tvs_params* P, const std::function<void()>& enqueue);
+std::vector<uint64_t> graph_key(const tvs_op* op, bool pdhg, int dtype, const void* b,
+                                const tvs_state* st, const tvs_params* P);
 void graph_run_key(tvs_ctx* ctx, const std::vector<uint64_t>& key,
                    const std::function<void()>& enqueue);
 void graph_cache_clear(tvs_ctx* ctx);
@@ -305,6 +310,16 @@ void gap_host(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, co
 template <typename T>
 void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
                   T* q, T* z, double* rel_gap);
+
+// Optional parts of a solver run: the learned prox in place of FGP and the
+// recording of the prox inputs.
+struct SolveExt {
+    tvs_cnn* cnn = nullptr;
+    double gap_tol = 0.0;
+    void* v_record = nullptr;   // device, max_record x H x W, the solver's dtype
+    int64_t max_record = 0;
+    int* gate = nullptr;        // device, one int per prox call (learned prox)
+};
 
 // learned prox (kernels_cnn.hip)
 namespace cnn {
@@ -363,6 +378,18 @@ void launch_adam(tvs_ctx* ctx, int n, float* p, const float* grad, float* m, flo
                  float b1, float b2, float c1, float c2, float eps);
 void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, uint16_t* wf_lo,
                  uint16_t* wb);
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* record);
+void launch_copy_if_off(tvs_ctx* ctx, size_t n, const int* flag, const float* src, float* dst);
+// Learned prox inside a solver run (capturable): allocations and lam set up
+// by prepare_solver_prox before capture; enqueue_solver_prox writes
+// P_lam(net(v)) into q, gates on its relative duality gap (device side) and
+// runs `iters` FGP iterations warm-started from it when the gap is above
+// tol.  Returns the buffer holding the final dual; *record (device) gets 1
+// if FGP ran.
+void prepare_solver_prox(tvs_cnn* c, int H, int W, double lam);
+bool fast_forward(const tvs_cnn* c);
+float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam, int nonneg,
+                           double tol, int iters, float* q, const FgpConfig& cfg, int* record);
 }  // namespace cnn
 
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
