@@ -292,7 +292,9 @@ tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slic
  *
  * Batches: v, z_target [n][H][W] and qt [n][2][H][W] are float32 device
  * buffers; lam_host is n doubles on the host.  Training loss:
- * L = sum (z - z_target)^2 / (2 n H W).  A tvs_cnn belongs to one context
+ * L = sum [(z - z_target)^2 + mu |q - q_target|^2] / (2 n H W), the dual
+ * term optional (q_target [n][2][H][W] device float32, NULL or mu = 0 drops
+ * it); it fixes the dual where z alone leaves it free (D z = 0).  A tvs_cnn belongs to one context
  * and uses its stream; it owns its parameters and scratch (grow-only). */
 typedef struct tvs_cnn tvs_cnn;
 
@@ -315,7 +317,8 @@ tvs_status tvs_cnn_forward(tvs_cnn* cnn, int n, int H, int W, const float* v,
  * for tvs_cnn_adam_step).  Synchronises when loss_out is set. */
 tvs_status tvs_cnn_loss_grad(tvs_cnn* cnn, int n, int H, int W, const float* v,
                              const double* lam_host, int nonneg, const float* z_target,
-                             double* loss_out, float* grad_out);
+                             const float* q_target, double mu, double* loss_out,
+                             float* grad_out);
 /* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) with the
  * gradient grad (device float32[param_count]) or, when grad is NULL, the one
  * kept by the last tvs_cnn_loss_grad. */
@@ -323,7 +326,7 @@ tvs_status tvs_cnn_adam_step(tvs_cnn* cnn, const float* grad, double lr);
 /* tvs_cnn_loss_grad followed by tvs_cnn_adam_step. */
 tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
                               const double* lam_host, int nonneg, const float* z_target,
-                              double lr, double* loss_out);
+                              const float* q_target, double mu, double lr, double* loss_out);
 /* Learned prox of one H x W image with a duality-gap gate: the network's
  * dual q = P_lam(qt) is written to q_out [2][H][W]; if its relative gap
  * gap(q) / P(z_q) (the gap of eq. (6) in the form gap(q) = sum_i lam

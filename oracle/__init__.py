@@ -96,7 +96,8 @@ def lib():
         L.orc_cnn_param_count.argtypes = []
         L.orc_cnn_param_count.restype = C.c_size_t
         L.orc_cnn_forward.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
-        L.orc_cnn_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
+        L.orc_cnn_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp,
+                                        C.c_double, dp]
         L.orc_cnn_loss_grad.restype = C.c_double
         L.orc_adam_step.argtypes = [C.c_size_t, dp, dp, dp, dp, C.c_int64, C.c_double,
                                     C.c_double, C.c_double, C.c_double]
@@ -331,14 +332,16 @@ def cnn_forward(v, lam, params, nonneg=0):
     return qt, z
 
 
-def cnn_loss_grad(v, lam, params, z_target, nonneg=0, want_grad=True):
-    """Returns (loss, grad or None)."""
+def cnn_loss_grad(v, lam, params, z_target, nonneg=0, want_grad=True, q_target=None, mu=0.0):
+    """Returns (loss, grad or None); the dual term needs q_target [n][2][H][W]."""
     v, lam = _batch(v, lam)
     n, H, W = v.shape
     params = _f64(params)
     zt = _f64(z_target).reshape(n, H, W)
+    qt = None if q_target is None else _f64(q_target).reshape(n, 2, H, W)
     g = np.empty(params.size) if want_grad else None
     loss = lib().orc_cnn_loss_grad(n, H, W, _p(v), _p(lam), int(nonneg), _p(params), _p(zt),
+                                   _p(qt) if qt is not None else None, float(mu),
                                    _p(g) if want_grad else None)
     return loss, g
 

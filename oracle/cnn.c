@@ -15,7 +15,10 @@
  *           x_l = max(pre_l, 0) for l = 1, 2, 3;  qt = pre_4 (2 channels)
  *   head    q = P_lam(qt)   (the ball projection of eq. (7), strict branch)
  *           z = P_X(v + div q)                 (u = b + div q, Sec. 2.1)
- *   loss    L = sum over the batch of (z - z_target)^2 / (2 * pixels)
+ *   loss    L = sum over the batch of [(z - z_target)^2 + mu |q - q_target|^2]
+ *               / (2 * pixels), the dual term optional (q_target = NULL or
+ *               mu = 0); it pins the dual where z alone leaves it free (where
+ *               D z = 0 any feasible dual with the same divergence fits)
  *
  * Channels 2 -> 32 -> 32 -> 32 -> 2, 3x3 kernels, zero padding.  The dual
  * output makes the duality gap of eq. (6) computable for every prediction,
@@ -172,7 +175,7 @@ void orc_cnn_forward(int nimg, int H, int W, const double* v, const double* lam,
  * grad (nullable) is overwritten.  Returns the loss. */
 double orc_cnn_loss_grad(int nimg, int H, int W, const double* v, const double* lam,
                          int nonneg, const double* params, const double* z_target,
-                         double* grad) {
+                         const double* q_target, double mu, double* grad) {
     size_t n = (size_t)H * W;
     double npx = (double)nimg * (double)n;
     size_t np = orc_cnn_param_count();
@@ -194,10 +197,18 @@ double orc_cnn_loss_grad(int nimg, int H, int W, const double* v, const double* 
             loss += d * d;
             gu[p] = (nonneg && !(a.u[p] > 0.0)) ? 0.0 : d / npx;
         }
+        const double* qtg = q_target ? q_target + 2 * b * n : NULL;
+        if (qtg && mu != 0.0)
+            for (size_t p = 0; p < 2 * n; ++p) {
+                double d = a.q[p] - qtg[p];
+                loss += mu * d * d;
+            }
         if (!grad) continue;
-        /* z = P_X(v + div q):  dL/dq = div^T gu = -D gu */
+        /* z = P_X(v + div q):  dL/dq = div^T gu = -D gu, plus the dual term */
         orc_grad(H, W, gu, gq);
         for (size_t p = 0; p < 2 * n; ++p) gq[p] = -gq[p];
+        if (qtg && mu != 0.0)
+            for (size_t p = 0; p < 2 * n; ++p) gq[p] += mu * (a.q[p] - qtg[p]) / npx;
         /* q = P_lam(qt) */
         double* qt = a.pre[ORC_CNN_LAYERS - 1];
         double* g4 = gpre[ORC_CNN_LAYERS - 1];

@@ -107,10 +107,11 @@ size_t orc_cnn_param_count(void);
  * z_out (nullable): [n][H][W] = P_X(v + div P_lam(qt)). */
 void orc_cnn_forward(int n, int H, int W, const double* v, const double* lam, int nonneg,
                      const double* params, double* qt_out, double* z_out);
-/* Loss sum (z - z_target)^2 / (2 n H W) and its gradient (nullable). */
+/* Loss sum [(z - z_target)^2 + mu |q - q_target|^2] / (2 n H W), q =
+ * P_lam(qt), q_target [n][2][H][W] nullable, and its gradient (nullable). */
 double orc_cnn_loss_grad(int n, int H, int W, const double* v, const double* lam,
                          int nonneg, const double* params, const double* z_target,
-                         double* grad);
+                         const double* q_target, double mu, double* grad);
 void orc_adam_step(size_t n, double* params, const double* grad, double* m, double* v,
                    int64_t step, double lr, double beta1, double beta2, double eps);
 

@@ -388,11 +388,13 @@ def tvs_cnn_forward(cnn: int, v, lam, nonneg: int = 0, qt=None, z=None) -> None:
                                 _ptr(_f32(z), n * H * W)))
 
 
-def tvs_cnn_loss_grad(cnn: int, v, lam, z_target, nonneg: int = 0, grad=None) -> float:
+def tvs_cnn_loss_grad(cnn: int, v, lam, z_target, nonneg: int = 0, grad=None, q_target=None,
+                      mu: float = 0.0) -> float:
     n, H, W = _batch_shape(_f32(v))
     loss = C.c_double()
     check(lib().tvs_cnn_loss_grad(C.c_void_p(cnn), n, H, W, _ptr(v), _lam_array(lam, n),
-                                  int(nonneg), _ptr(_f32(z_target), n * H * W), C.byref(loss),
+                                  int(nonneg), _ptr(_f32(z_target), n * H * W),
+                                  _ptr(_f32(q_target), 2 * n * H * W), float(mu), C.byref(loss),
                                   _ptr(_f32(grad), tvs_cnn_param_count())))
     return loss.value
 
@@ -403,11 +405,12 @@ def tvs_cnn_adam_step(cnn: int, lr: float, grad=None) -> None:
 
 
 def tvs_cnn_train_step(cnn: int, v, lam, z_target, lr: float, nonneg: int = 0,
-                       want_loss: bool = True):
+                       want_loss: bool = True, q_target=None, mu: float = 0.0):
     n, H, W = _batch_shape(_f32(v))
     loss = C.c_double()
     check(lib().tvs_cnn_train_step(C.c_void_p(cnn), n, H, W, _ptr(v), _lam_array(lam, n),
-                                   int(nonneg), _ptr(_f32(z_target), n * H * W), float(lr),
+                                   int(nonneg), _ptr(_f32(z_target), n * H * W),
+                                   _ptr(_f32(q_target), 2 * n * H * W), float(mu), float(lr),
                                    C.byref(loss) if want_loss else None))
     return loss.value if want_loss else None
 

@@ -107,10 +107,11 @@ PROTOTYPES = {
     "tvs_cnn_get_params": (C.c_int, [vp, vp]),
     "tvs_cnn_set_params": (C.c_int, [vp, vp]),
     "tvs_cnn_forward": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, vp]),
-    "tvs_cnn_loss_grad": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, dp, vp]),
+    "tvs_cnn_loss_grad": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, vp,
+                                    C.c_double, dp, vp]),
     "tvs_cnn_adam_step": (C.c_int, [vp, vp, C.c_double]),
-    "tvs_cnn_train_step": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp,
-                                     C.c_double, dp]),
+    "tvs_cnn_train_step": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, dp, C.c_int, vp, vp,
+                                     C.c_double, C.c_double, dp]),
     "tvs_cnn_prox": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_double, C.c_int, C.c_double,
                                C.c_int, vp, vp, ip, dp]),
     "tvs_cnn_set_fast_forward": (C.c_int, [vp, C.c_int]),

@@ -144,7 +144,7 @@ static void forward_convs(tvs_cnn* c, int n, int H, int W, const float* v, float
 }
 
 static void loss_grad(tvs_cnn* c, int n, int H, int W, const float* v, int nonneg,
-                      const float* zt, double* loss_out) {
+                      const float* zt, const float* qtg, double mu, double* loss_out) {
     const size_t npx = (size_t)n * H * W;
     float* qt = (float*)grow(c, tvs_cnn::B_QT, npx * 2 * sizeof(float));
     float* gu = (float*)grow(c, tvs_cnn::B_GU, npx * sizeof(float));
@@ -172,6 +172,8 @@ static void loss_grad(tvs_cnn* c, int n, int H, int W, const float* v, int nonne
     h.v = v;
     h.lam = lam;
     h.z_target = zt;
+    h.q_target = (qtg && mu != 0.0) ? qtg : nullptr;
+    h.mu = (float)mu;
     h.gu = gu;
     h.inv_npx = (float)(1.0 / (double)npx);
     h.loss_part = lossp;
@@ -446,14 +448,15 @@ extern "C" tvs_status tvs_cnn_forward(tvs_cnn* cnn, int n, int H, int W, const f
 
 extern "C" tvs_status tvs_cnn_loss_grad(tvs_cnn* cnn, int n, int H, int W, const float* v,
                                         const double* lam_host, int nonneg,
-                                        const float* z_target, double* loss_out,
-                                        float* grad_out) {
+                                        const float* z_target, const float* q_target, double mu,
+                                        double* loss_out, float* grad_out) {
     return guarded_cnn([&] {
         check_cnn(cnn);
         check_batch(n, H, W);
         TVS_REQUIRE(v && z_target, TVS_ERR_INVALID_ARG, "null pointer");
+        TVS_REQUIRE(std::isfinite(mu) && mu >= 0, TVS_ERR_INVALID_ARG, "mu >= 0 required");
         set_lam(cnn, n, lam_host);
-        loss_grad(cnn, n, H, W, v, nonneg ? 1 : 0, z_target, loss_out);
+        loss_grad(cnn, n, H, W, v, nonneg ? 1 : 0, z_target, q_target, mu, loss_out);
         if (grad_out)
             TVS_HIP(hipMemcpyAsync(grad_out, cnn->grad, NPARAM * sizeof(float),
                                    hipMemcpyDeviceToDevice, cnn->ctx->stream));
@@ -469,13 +472,15 @@ extern "C" tvs_status tvs_cnn_adam_step(tvs_cnn* cnn, const float* grad, double 
 
 extern "C" tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
                                          const double* lam_host, int nonneg,
-                                         const float* z_target, double lr, double* loss_out) {
+                                         const float* z_target, const float* q_target,
+                                         double mu, double lr, double* loss_out) {
     return guarded_cnn([&] {
         check_cnn(cnn);
         check_batch(n, H, W);
         TVS_REQUIRE(v && z_target, TVS_ERR_INVALID_ARG, "null pointer");
+        TVS_REQUIRE(std::isfinite(mu) && mu >= 0, TVS_ERR_INVALID_ARG, "mu >= 0 required");
         set_lam(cnn, n, lam_host);
-        loss_grad(cnn, n, H, W, v, nonneg ? 1 : 0, z_target, loss_out);
+        loss_grad(cnn, n, H, W, v, nonneg ? 1 : 0, z_target, q_target, mu, loss_out);
         adam(cnn, nullptr, lr);
     });
 }

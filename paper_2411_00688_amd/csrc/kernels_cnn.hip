@@ -373,12 +373,10 @@ __global__ void head_fwd_kernel(HeadArgs a) {
         const float lam = a.lam[img];
         const float* qy = a.qt + (size_t)img * 2 * plane;
         const float* qx = qy + plane;
+        const float sc = ball_scale_f(qy[p], qx[p], lam);
         float d = 0.f;
-        if (i < H - 1 || j < W - 1) {
-            const float sc = ball_scale_f(qy[p], qx[p], lam);
-            if (i < H - 1) d += qy[p] * sc;
-            if (j < W - 1) d += qx[p] * sc;
-        }
+        if (i < H - 1) d += qy[p] * sc;
+        if (j < W - 1) d += qx[p] * sc;
         if (i > 0) d -= qy[p - W] * ball_scale_f(qy[p - W], qx[p - W], lam);
         if (j > 0) d -= qx[p - 1] * ball_scale_f(qy[p - 1], qx[p - 1], lam);
         const float u = a.v[idx] + d;
@@ -389,6 +387,11 @@ __global__ void head_fwd_kernel(HeadArgs a) {
             const float e = z - a.z_target[idx];
             sq += e * e;
             a.gu[idx] = act ? e * a.inv_npx : 0.f;
+            if (a.q_target) {
+                const float* tg = a.q_target + (size_t)img * 2 * plane;
+                const float ry = qy[p] * sc - tg[p], rx = qx[p] * sc - tg[plane + p];
+                sq += a.mu * (ry * ry + rx * rx);
+            }
         }
     }
     if (!a.z_target) return;
@@ -401,7 +404,8 @@ __global__ void head_fwd_kernel(HeadArgs a) {
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = (double)s_red[0];
 }
 
-// g_qt = J_{P_lam}(qt)^T (-D g_u), stored channel-last BF16 (2 channels)
+// g_qt = J_{P_lam}(qt)^T (-D g_u + mu (q - q_target) / pixels), stored
+// channel-last BF16 (2 channels)
 __global__ void head_bwd_kernel(HeadArgs a) {
     const int H = a.H, W = a.W;
     const size_t plane = (size_t)H * W;
@@ -419,12 +423,19 @@ __global__ void head_bwd_kernel(HeadArgs a) {
         const float qx = a.qt[(size_t)img * 2 * plane + plane + p];
         float oy = gy, ox = gx;
         const float n2 = qy * qy + qx * qx;
+        if (a.q_target) {
+            const float sc = ball_scale_f(qy, qx, lam);
+            const float* tg = a.q_target + (size_t)img * 2 * plane;
+            oy += a.mu * (qy * sc - tg[p]) * a.inv_npx;
+            ox += a.mu * (qx * sc - tg[plane + p]) * a.inv_npx;
+        }
+        const float by = oy, bx = ox;
         if (n2 > lam * lam) {
             const float rn = __builtin_amdgcn_rsqf(fmaxf(n2, 1e-37f));
             const float ny = qy * rn, nx = qx * rn, s = lam * rn;
-            const float dot = ny * gy + nx * gx;
-            oy = s * (gy - ny * dot);
-            ox = s * (gx - nx * dot);
+            const float dot = ny * by + nx * bx;
+            oy = s * (by - ny * dot);
+            ox = s * (bx - nx * dot);
         }
         *(uint32_t*)&a.gq_bf[idx * 2] = (uint32_t)f2bf(oy) | ((uint32_t)f2bf(ox) << 16);
     }

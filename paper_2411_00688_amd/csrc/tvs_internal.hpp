@@ -361,6 +361,8 @@ struct HeadArgs {
     const float* lam = nullptr;     // [n]
     float* z = nullptr;             // nullable
     const float* z_target = nullptr;// training only
+    const float* q_target = nullptr;// training, optional dual target [n][2][H][W]
+    float mu = 0.f;                 // weight of the dual term
     float* gu = nullptr;            // training: dL/du [n][H][W]
     float inv_npx = 0.f;
     double* loss_part = nullptr;    // [blocks]

@@ -89,16 +89,18 @@ def test_forward_sampled_at_512(cnn):
         assert rel_l2(got[:, r], row_ref) < FWD_TOL[False], r
 
 
-@pytest.mark.parametrize("nonneg", [0, 1])
-def test_gradient_matches_oracle(cnn, nonneg):
+@pytest.mark.parametrize("nonneg,mu", [(0, 0.0), (1, 0.0), (1, 3.0)])
+def test_gradient_matches_oracle(cnn, nonneg, mu):
     P = set_params(cnn, 300 + nonneg)
     n, H, W = 3, 29, 40
     v, lam = inputs(n, H, W, 400 + nonneg, nonneg)
-    _, zt = O.cnn_forward(v, lam, synth.cnn_params(999, 0.5), nonneg)
+    qtg, zt = O.cnn_forward(v, lam, synth.cnn_params(999, 0.5), nonneg)
     zt = synth.to_f32_exact(zt)
+    qtg = synth.to_f32_exact(np.stack([O.proj_ball(qtg[k], lam[k]) for k in range(n)])) if mu else None
     grad = torch.empty(T.tvs_cnn_param_count(), dtype=F32, device="cuda")
-    loss = T.tvs_cnn_loss_grad(cnn, dev(v, F32), lam, dev(zt, F32), nonneg, grad)
-    loss_ref, g_ref = O.cnn_loss_grad(v, lam, P, zt, nonneg)
+    loss = T.tvs_cnn_loss_grad(cnn, dev(v, F32), lam, dev(zt, F32), nonneg, grad,
+                               q_target=dev(qtg, F32) if mu else None, mu=mu)
+    loss_ref, g_ref = O.cnn_loss_grad(v, lam, P, zt, nonneg, q_target=qtg, mu=mu)
     g = host(grad)
     print(f"loss rel {abs(loss - loss_ref) / loss_ref:.2e} grad rel {rel_l2(g, g_ref):.2e} "
           f"cos {cosine(g, g_ref):.6f}")

@@ -108,19 +108,26 @@ def test_loss_is_half_mean_square():
     P = he_params(rng)
     v = rng.random((2, 6, 5))
     zt = rng.random((2, 6, 5))
-    _, z = O.cnn_forward(v, [0.1, 0.4], P)
-    loss, _ = O.cnn_loss_grad(v, [0.1, 0.4], P, zt, want_grad=False)
+    qtg = rng.standard_normal((2, 2, 6, 5)) * 0.1
+    lam = np.array([0.1, 0.4])
+    qt, z = O.cnn_forward(v, lam, P)
+    loss, _ = O.cnn_loss_grad(v, lam, P, zt, want_grad=False)
     assert abs(loss - 0.5 * np.mean((z - zt) ** 2)) < 1e-15
+    q = np.stack([O.proj_ball(qt[b], lam[b]) for b in range(2)])
+    loss2, _ = O.cnn_loss_grad(v, lam, P, zt, want_grad=False, q_target=qtg, mu=0.7)
+    ref = 0.5 * (np.sum((z - zt) ** 2) + 0.7 * np.sum((q - qtg) ** 2)) / z.size
+    assert abs(loss2 - ref) < 1e-15
 
 
-@pytest.mark.parametrize("nonneg,seed", [(0, 21), (1, 22)])
-def test_gradient_central_differences(nonneg, seed):
+@pytest.mark.parametrize("nonneg,seed,mu", [(0, 21, 0.0), (1, 22, 0.0), (1, 23, 2.0)])
+def test_gradient_central_differences(nonneg, seed, mu):
     rng = np.random.default_rng(seed)
     P = he_params(rng, scale=1.5)
     v = rng.random((2, 6, 5)) - 0.3 * nonneg
     lam = np.array([0.08, 0.3])
     zt = rng.random((2, 6, 5)) * 0.5
-    loss, g = O.cnn_loss_grad(v, lam, P, zt, nonneg)
+    qtg = rng.standard_normal((2, 2, 6, 5)) * 0.1 if mu else None
+    loss, g = O.cnn_loss_grad(v, lam, P, zt, nonneg, q_target=qtg, mu=mu)
     # Loss ~ 0.1: the rounding error of a central difference is ~ 2e-17 / h,
     # the truncation error ~ h^2.  A random direction moves every
     # pre-activation, so its step stays small enough not to cross a ReLU or
@@ -128,7 +135,7 @@ def test_gradient_central_differences(nonneg, seed):
     h_dir, h = 1e-6, 5e-5
 
     def L(p):
-        return O.cnn_loss_grad(v, lam, p, zt, nonneg, want_grad=False)[0]
+        return O.cnn_loss_grad(v, lam, p, zt, nonneg, want_grad=False, q_target=qtg, mu=mu)[0]
 
     # random directions: every parameter at once
     for _ in range(4):
