@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-tta", action="store_true", help="skip time-to-accuracy runs")
     ap.add_argument("--fgp-size", type=int, default=8192)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-prox training and runs")
     return ap.parse_args()
 
 
@@ -130,6 +131,11 @@ def main():
     if not args.no_batched:
         batched = batched_bench(T, ctx)
 
+    # ---- learned prox: trained here on the method's own prox inputs
+    learned_res = None
+    if not args.no_learned:
+        learned_res = learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta)
+
     # ---- CPU oracle baseline on this host
     cpu = None
     if not args.no_cpu:
@@ -160,6 +166,7 @@ def main():
         "roofline": roof,
         "tv_prox_hbm": fgp_big,
         "batched": batched,
+        "learned": learned_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -306,6 +313,93 @@ def fgp_hbm(T, ctx, n, Kin):
     del v, q, z
     torch.cuda.empty_cache()
     log(f"FGP {n}^2: {res}")
+    return res
+
+
+def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
+    """The learned prox on the CT workload.  Training pairs: the prox inputs
+    of PDHGSkip-2 runs on three other phantoms (same geometry, alpha, p),
+    targets from 300 FGP iterations; 3000 Adam steps of two 512^2 images,
+    dual-target weight 0.1.  Held out: the prox inputs of the timed run.
+    Reports (i) cold prox calls: duality gap after the method's 50 FGP
+    iterations from the zero dual and from the network's dual, and the FGP
+    iterations the network's start needs to match the zero start; (ii)
+    PDHGSkip-2 with the gap-gated learned prox (gate 1e-3) to 1e-4."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2411_00688_amd import learned
+    dev = torch.device("cuda:0")
+    N, na, nd, Kin, p = w.H, w.n_ang, w.n_det, w.inner_iters, w.p
+    lam = w.alpha * sigma / p
+
+    def problem(i):
+        u, eta = synth.make_inputs(w, seed_index=i)
+        Au = torch.empty(na, nd, dtype=torch.float64, device=dev)
+        T.tvs_op_apply(op, torch.tensor(u, device=dev), Au)
+        return (Au + w.noise * Au.max() * torch.tensor(eta, device=dev)).float().contiguous()
+
+    def record(bb, i):
+        return learned.record_prox_inputs(op, bb, w.alpha, sigma, p, w.outer_iters, Kin, 320,
+                                          nonneg=1, seed=synth.coin_seed(w.index, i),
+                                          dual_step=tau, H=N, W=N)
+
+    t0 = time.perf_counter()
+    V = torch.cat([record(problem(i), i) for i in (1, 2, 3)])
+    Z, Q = learned.fgp_targets(ctx, V, lam, 300, nonneg=1)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    cnn = T.tvs_cnn_create(ctx, 7)
+    secs, loss = learned.train(cnn, V, Z, Q, lam, steps=steps, batch=2, lr=1e-3, mu=0.1,
+                               nonneg=1, log=lambda *a: None)
+    log(f"learned prox: {V.shape[0]} pairs ({t_data:.1f} s), {steps} steps in {secs:.1f} s")
+    Vt = record(b, 0)[::8].contiguous()
+    res = {"pairs": int(V.shape[0]), "lam": lam, "data_s": round(t_data, 2),
+           "train_steps": steps, "train_s": round(secs, 2),
+           "train_ms_per_step": round(1e3 * secs / steps, 3), "final_loss": loss}
+    g50 = learned.cold_start_gaps(ctx, cnn, Vt, lam, Kin, nonneg=1)
+    zero50 = float(np.median(g50["zero"]))
+    res["cold_gap_after_50"] = {"zero_start": zero50, "network_start": float(np.median(g50["cnn"]))}
+    match = None
+    for k in range(5, Kin + 1, 5):
+        if np.median(learned.cold_start_gaps(ctx, cnn, Vt, lam, k, nonneg=1)["cnn"]) <= zero50:
+            match = k
+            break
+    res["network_start_iters_to_match_zero_start_50"] = match
+    # times of the pieces
+    qb = torch.empty(2, N, N, device=dev)
+    zb = torch.empty(N, N, device=dev)
+    t_fgp = _evtime(lambda: T.tvs_tv_prox(ctx, Vt[0], lam, Kin, 1, qb, zb), 5)
+    t_fin = _evtime(lambda: T.tvs_tv_prox(ctx, Vt[0], lam, 0, 1, qb, zb), 5)
+    qt = torch.empty(1, 2, N, N, device=dev)
+    fwd = {}
+    for fast in (False, True):
+        T.tvs_cnn_set_fast_forward(cnn, fast)
+        fwd["bf16x1" if fast else "bf16x3"] = round(
+            _evtime(lambda: T.tvs_cnn_forward(cnn, Vt[0], lam, 1, qt, None), 10), 4)
+    T.tvs_cnn_set_fast_forward(cnn, False)
+    per_it = (t_fgp - t_fin) / Kin
+    res["ms"] = {"fgp_50": round(t_fgp, 4), "fgp_per_iter": round(per_it, 5),
+                 "network_forward": fwd}
+    if match:
+        res["cold_prox_ms_to_zero_start_gap"] = {
+            "zero_start": round(t_fgp, 4),
+            "network_start": round(fwd["bf16x3"] + t_fin + match * per_it, 4)}
+    # the solver with the gap-gated learned prox
+    phis = (tta or {}).get("phi_star")
+    if phis:
+        x = torch.zeros(N, N, device=dev)
+        h, q, y = torch.zeros_like(x), torch.zeros(2, N, N, device=dev), torch.zeros(na, nd, device=dev)
+        r = T.tvs_pdhgskip_ex(op, b, x, h, q, y, w.alpha, sigma, tau, p, w.outer_iters, Kin,
+                              nonneg=1, seed=seed, want_obj=True, cnn=cnn, gap_tol=1e-3)
+        rel = np.abs(r["obj"] - phis) / phis
+        bad = np.nonzero(rel > 1e-4)[0]
+        kstar = int(bad[-1] + 2) if len(bad) else 1
+        res["pdhgskip_learned_gate_1e-3"] = {
+            "iters_to_1e-4": kstar if kstar <= w.outer_iters else None,
+            "final_rel": float(rel[-1]), "prox_calls": int(r["n_prox"]),
+            "fgp_fallbacks": int(r["n_fallback"])}
+    T.tvs_cnn_destroy(cnn)
     return res
 
 
