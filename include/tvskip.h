@@ -142,7 +142,12 @@ tvs_status tvs_objective(tvs_op* op, tvs_dtype dtype, const void* b, const void*
 /* ------------------------------------------------------------- FGP tuning
  * The FGP kernel is compiled for several output tiles (tile_w x tile_h) and
  * temporal depths (steps: FGP iterations fused per launch, with a halo of
- * `steps` pixels).  The choice is kept per (H, W, dtype) in the context. */
+ * `steps` pixels), each with 256 threads.  The context keeps a tuning table:
+ * entries per exact size (H, W, dtype), per size class (H and W each
+ * rounded up to a power of two, at least 16; written by the autotuner next
+ * to the exact entry) and per batched slice count.  An H x W prox uses the
+ * exact entry, else its size class entry, else the default (32 x 32, 4
+ * steps). */
 int tvs_fgp_variant_count(void);
 /* Shape of variant `index` (host outputs). */
 tvs_status tvs_fgp_variant(int index, int* tile_w, int* tile_h, int* steps);
@@ -157,6 +162,24 @@ tvs_status tvs_fgp_set_variant(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int 
  * memory. */
 tvs_status tvs_fgp_autotune(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int inner_iters,
                             int reps, int* best_index, double* ms_per_iter_out);
+/* The variant an H x W prox would use now (*index, host) and its measured
+ * milliseconds per FGP iteration (*ms_per_iter, nullable; -1 when set by
+ * hand or the default). */
+tvs_status tvs_fgp_query(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int* index,
+                         double* ms_per_iter);
+/* Remove every tuning entry of the context. */
+tvs_status tvs_tune_clear(tvs_ctx* ctx);
+/* Save the tuning table as JSON: {"format": "tvskip-fgp-tune/1", "arch":
+ * <GPU architecture, e.g. "gfx950">, "entries": [{"kind": "image" | "class" |
+ * "batch", "dtype": "f32" | "f64", "H", "W" (image, class) or "n_slices"
+ * (batch), "tile_w", "tile_h", "steps", "ms_per_iter"}, ...]}.  Written to
+ * path + ".tmp" and renamed. */
+tvs_status tvs_tune_save(tvs_ctx* ctx, const char* path);
+/* Load a tuning file: entries replace those with the same key.  A file made
+ * on another architecture is TVS_ERR_UNSUPPORTED, a malformed one
+ * TVS_ERR_INVALID_ARG (the table is unchanged in both cases), an entry naming
+ * a variant this library does not compile TVS_ERR_UNSUPPORTED. */
+tvs_status tvs_tune_load(tvs_ctx* ctx, const char* path);
 
 /* --------------------------------------------------------------------- coin
  * theta_k ~ Bernoulli(p), i.i.d. in k (Alg. "ProxSkip", Alg. "PDHGSkip-2"),
@@ -265,6 +288,16 @@ tvs_status tvs_proxskip_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
 /* FGP tile variant used by tvs_proxskip_batched for batches of n_slices
  * slices in this context (-1 restores the default). */
 tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices, int index);
+/* Times every FGP variant on one FGP pass over a batch with these slice
+ * sizes and parameters (all slices active, seeded random data on private
+ * pools; offsets are ignored), keeps the fastest for n_slices slices.
+ * Outputs as tvs_fgp_autotune. */
+tvs_status tvs_fgp_autotune_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
+                                    const tvs_slice* slices, int inner_iters, int reps,
+                                    int* best_index, double* ms_per_iter_out);
+/* The variant a batch of n_slices slices would use now. */
+tvs_status tvs_fgp_query_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices, int* index,
+                                 double* ms_per_iter);
 
 /* ------------------------------------------------------------ learned prox
  * A learned replacement for the inner TV-prox solver of Sec. 3 (the prox of

@@ -23,7 +23,8 @@ __all__ = [
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
-    "tvs_proxskip_batched", "tvs_fgp_set_variant_batched",
+    "tvs_proxskip_batched", "tvs_fgp_set_variant_batched", "tvs_fgp_autotune_batched",
+    "tvs_fgp_query", "tvs_fgp_query_batched", "tvs_tune_clear", "tvs_tune_save", "tvs_tune_load",
     "tvs_cnn_create", "tvs_cnn_destroy", "tvs_cnn_param_count", "tvs_cnn_get_params",
     "tvs_cnn_set_params", "tvs_cnn_forward", "tvs_cnn_loss_grad", "tvs_cnn_adam_step",
     "tvs_cnn_train_step", "tvs_cnn_prox", "tvs_cnn_set_fast_forward", "tvs_cnn_save",
@@ -291,7 +292,35 @@ def tvs_fgp_autotune(ctx: int, dtype: int, H: int, W: int, inner_iters: int = 50
     return best.value, ms.tolist()
 
 
+def tvs_fgp_query(ctx: int, dtype: int, H: int, W: int):
+    """(variant index, measured ms per FGP iteration or -1) an H x W prox uses."""
+    idx, ms = C.c_int(), C.c_double()
+    check(lib().tvs_fgp_query(C.c_void_p(ctx), int(dtype), int(H), int(W), C.byref(idx),
+                              C.byref(ms)))
+    return idx.value, ms.value
+
+
+def tvs_tune_clear(ctx: int) -> None:
+    check(lib().tvs_tune_clear(C.c_void_p(ctx)))
+
+
+def tvs_tune_save(ctx: int, path: str) -> None:
+    check(lib().tvs_tune_save(C.c_void_p(ctx), str(path).encode()))
+
+
+def tvs_tune_load(ctx: int, path: str) -> None:
+    check(lib().tvs_tune_load(C.c_void_p(ctx), str(path).encode()))
+
+
 # ------------------------------------------------------------ batched form
+def _slice_array(slices):
+    n = len(slices)
+    arr = (tvs_slice * n)()
+    for i, sl in enumerate(slices):
+        arr[i] = tvs_slice(int(sl["H"]), int(sl["W"]), int(sl.get("offset", 0)),
+                           float(sl["alpha"]), float(sl["p"]), int(sl.get("seed", 0)),
+                           int(sl.get("stream_id", 0)))
+    return arr
 def tvs_proxskip_batched(ctx: int, slices, b_pool, x_pool, h_pool, q_pool, step, outer_iters,
                          inner_iters, nonneg=0, k0=0, graph=False, fgp_variant=-1):
     """Batched ProxSkip (A = I) in place on the pools.  `slices`: sequence of
@@ -322,6 +351,25 @@ def tvs_proxskip_batched(ctx: int, slices, b_pool, x_pool, h_pool, q_pool, step,
 
 def tvs_fgp_set_variant_batched(ctx: int, dtype: int, n_slices: int, index: int) -> None:
     check(lib().tvs_fgp_set_variant_batched(C.c_void_p(ctx), int(dtype), int(n_slices), int(index)))
+
+
+def tvs_fgp_autotune_batched(ctx: int, dtype: int, slices, inner_iters: int = 50, reps: int = 2):
+    """Times every FGP variant on one pass over a batch of these slices; keeps
+    the fastest for len(slices) slices.  Returns (best_index, [ms per iter])."""
+    import numpy as np
+    ms = np.zeros(tvs_fgp_variant_count())
+    best = C.c_int()
+    check(lib().tvs_fgp_autotune_batched(C.c_void_p(ctx), int(dtype), len(slices),
+                                         _slice_array(slices), int(inner_iters), int(reps),
+                                         C.byref(best), ms.ctypes.data_as(C.POINTER(C.c_double))))
+    return best.value, ms.tolist()
+
+
+def tvs_fgp_query_batched(ctx: int, dtype: int, n_slices: int):
+    idx, ms = C.c_int(), C.c_double()
+    check(lib().tvs_fgp_query_batched(C.c_void_p(ctx), int(dtype), int(n_slices), C.byref(idx),
+                                      C.byref(ms)))
+    return idx.value, ms.value
 
 
 # ---------------------------------------------------------------- learned prox

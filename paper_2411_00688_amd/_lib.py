@@ -101,6 +101,13 @@ PROTOTYPES = {
     "tvs_proxskip_batched": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(tvs_slice), vp, vp, vp, vp,
                                        C.POINTER(tvs_batch_params), C.POINTER(C.c_int64)]),
     "tvs_fgp_set_variant_batched": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+    "tvs_fgp_autotune_batched": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(tvs_slice), C.c_int,
+                                           C.c_int, ip, dp]),
+    "tvs_fgp_query": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, ip, dp]),
+    "tvs_fgp_query_batched": (C.c_int, [vp, C.c_int, C.c_int, ip, dp]),
+    "tvs_tune_clear": (C.c_int, [vp]),
+    "tvs_tune_save": (C.c_int, [vp, C.c_char_p]),
+    "tvs_tune_load": (C.c_int, [vp, C.c_char_p]),
     "tvs_cnn_create": (C.c_int, [vp, C.c_uint64, C.POINTER(vp)]),
     "tvs_cnn_destroy": (None, [vp]),
     "tvs_cnn_param_count": (C.c_int64, []),

@@ -112,19 +112,25 @@ const T* beta_table_dev(tvs_ctx* ctx, int n) {
 }
 
 FgpConfig fgp_config(tvs_ctx* ctx, int H, int W, int dtype_bytes) {
+    auto it = ctx->fgp_tuned.find(tune_key(TK_IMAGE, H, W, dtype_bytes));
+    if (it != ctx->fgp_tuned.end()) return it->second.cfg;
+    it = ctx->fgp_tuned.find(tune_key(TK_CLASS, size_class(H), size_class(W), dtype_bytes));
+    if (it != ctx->fgp_tuned.end()) return it->second.cfg;
     FgpConfig c;
-    auto it = ctx->fgp_tuned.find(fgp_key(H, W, dtype_bytes));
-    if (it != ctx->fgp_tuned.end()) return it->second;
-    if (H == 0) {
-        // batched form (key (0, n_slices)): large total sizes favour wide tiles
-        c.tile_w = 64;
-        c.tile_h = 16;
-        c.steps = 4;
-    } else {
-        c.tile_w = 32;
-        c.tile_h = 32;
-        c.steps = 4;
-    }
+    c.tile_w = 32;
+    c.tile_h = 32;
+    c.steps = 4;
+    return c;
+}
+
+FgpConfig fgp_config_batched(tvs_ctx* ctx, int n_slices, int dtype_bytes) {
+    auto it = ctx->fgp_tuned.find(tune_key(TK_BATCH, n_slices, 0, dtype_bytes));
+    if (it != ctx->fgp_tuned.end()) return it->second.cfg;
+    // large total sizes favour wide tiles
+    FgpConfig c;
+    c.tile_w = 64;
+    c.tile_h = 16;
+    c.steps = 4;
     return c;
 }
 

@@ -63,7 +63,7 @@ void run_batched(tvs_ctx* ctx, int n, const tvs_slice* S, const T* b, T* x, T* h
         TVS_REQUIRE(P->fgp_variant < fgp_variant_count(), TVS_ERR_INVALID_ARG, "bad FGP variant");
         cfg = fgp_variant(P->fgp_variant);
     } else {
-        cfg = fgp_config(ctx, 0, n, (int)sizeof(T));
+        cfg = fgp_config_batched(ctx, n, (int)sizeof(T));
     }
 
     // --------------------------------------------------------------- plan
@@ -171,7 +171,132 @@ void run_batched(tvs_ctx* ctx, int n, const tvs_slice* S, const T* b, T* x, T* h
         for (int s = 0; s < n; ++s) nprox_out[s] = pl.nprox[s];
 }
 
+// Times every compiled FGP variant on one FGP pass over the whole batch
+// (every slice active), on private pools with seeded random data laid out
+// back to back; keeps the fastest for this slice count.
+template <typename T>
+void autotune_batched(tvs_ctx* ctx, int n, const tvs_slice* S, int iters, int reps, int* best,
+                      double* ms_out) {
+    TVS_REQUIRE(n >= 1, TVS_ERR_SHAPE, "n_slices >= 1 required");
+    std::vector<BSlice<T>> hs(n);
+    size_t total = 0;
+    for (int s = 0; s < n; ++s) {
+        TVS_REQUIRE(S[s].H >= 1 && S[s].W >= 1, TVS_ERR_SHAPE, "slice sizes >= 1 required");
+        TVS_REQUIRE(S[s].p > 0 && S[s].p <= 1 && S[s].alpha >= 0, TVS_ERR_INVALID_ARG,
+                    "slice p in (0, 1] and alpha >= 0 required");
+        hs[s].H = S[s].H;
+        hs[s].W = S[s].W;
+        hs[s].off = (int64_t)total;
+        hs[s].lam = (T)(S[s].alpha / S[s].p);
+        hs[s].coef = T(0);
+        hs[s].rate = T(1);
+        total += (size_t)S[s].H * S[s].W;
+    }
+    std::vector<T> hv(total);
+    for (size_t i = 0; i < total; ++i)
+        hv[i] = (T)((double)(splitmix_mix(i + 7) >> 11) * (1.0 / 9007199254740992.0));
+    struct Tmp {
+        std::vector<void*> ptrs;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Tmp() {
+            for (void* p : ptrs) (void)hipFree(p);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+        void* alloc(size_t bytes) {
+            void* p = nullptr;
+            TVS_HIP(hipMalloc(&p, bytes));
+            ptrs.push_back(p);
+            return p;
+        }
+    } tmp;
+    T* v = (T*)tmp.alloc(total * sizeof(T));
+    T* q = (T*)tmp.alloc(2 * total * sizeof(T));
+    BSlice<T>* d_sl = (BSlice<T>*)tmp.alloc(n * sizeof(BSlice<T>));
+    int* d_list = (int*)tmp.alloc((size_t)(3 * n + 2) * sizeof(int));
+    TVS_HIP(hipMemcpy(v, hv.data(), total * sizeof(T), hipMemcpyHostToDevice));
+    TVS_HIP(hipMemcpy(d_sl, hs.data(), n * sizeof(BSlice<T>), hipMemcpyHostToDevice));
+    TVS_HIP(hipEventCreate(&tmp.e0));
+    TVS_HIP(hipEventCreate(&tmp.e1));
+    scratch(ctx, S_Q1, 2 * total * sizeof(T));
+    scratch(ctx, S_Q2, 2 * total * sizeof(T));
+    scratch(ctx, S_Q3, 2 * total * sizeof(T));
+    beta_table_dev<T>(ctx, iters + 1);
+    double best_ms = 1e300;
+    int best_i = -1;
+    for (int vi = 0; vi < fgp_variant_count(); ++vi) {
+        const FgpConfig c = fgp_variant(vi);
+        if (find_variant_index(c, (int)sizeof(T)) < 0) {
+            if (ms_out) ms_out[vi] = -1.0;
+            continue;
+        }
+        // work lists with every slice active: act, FGP tile prefix, 32 x 32 prefix
+        std::vector<int> ints;
+        for (int s = 0; s < n; ++s) ints.push_back(s);
+        int cf = 0, cn = 0;
+        ints.push_back(0);
+        for (int s = 0; s < n; ++s) ints.push_back(cf += tiles_of(S[s].H, S[s].W, c.tile_w, c.tile_h));
+        ints.push_back(0);
+        for (int s = 0; s < n; ++s) ints.push_back(cn += tiles_of(S[s].H, S[s].W, 32, 32));
+        TVS_HIP(hipMemcpy(d_list, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice));
+        BatchLists L;
+        L.n_act = n;
+        L.act = d_list;
+        L.pref_fgp = d_list + n;
+        L.pref_fin = d_list + 2 * n + 1;
+        L.tiles_fgp = cf;
+        L.tiles_fin = cn;
+        launch_fill<T>(ctx, 2 * total, T(0), q);
+        run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);  // warm-up
+        TVS_HIP(hipEventRecord(tmp.e0, ctx->stream));
+        for (int r = 0; r < reps; ++r) run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);
+        TVS_HIP(hipEventRecord(tmp.e1, ctx->stream));
+        TVS_HIP(hipEventSynchronize(tmp.e1));
+        float ms = 0;
+        TVS_HIP(hipEventElapsedTime(&ms, tmp.e0, tmp.e1));
+        const double per_iter = (double)ms / ((double)reps * iters);
+        if (ms_out) ms_out[vi] = per_iter;
+        if (per_iter < best_ms) {
+            best_ms = per_iter;
+            best_i = vi;
+        }
+    }
+    TVS_HIP(hipStreamSynchronize(ctx->stream));
+    TuneEntry e;
+    e.cfg = fgp_variant(best_i);
+    e.ms_per_iter = best_ms;
+    ctx->fgp_tuned[tune_key(TK_BATCH, n, 0, (int)sizeof(T))] = e;
+    if (best) *best = best_i;
+}
+
 }  // namespace
+
+extern "C" tvs_status tvs_fgp_autotune_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
+                                               const tvs_slice* slices, int inner_iters, int reps,
+                                               int* best_index, double* ms_per_iter_out) {
+    try {
+        TVS_REQUIRE(ctx && slices, TVS_ERR_INVALID_ARG, "null pointer");
+        TVS_REQUIRE(dtype == TVS_F32 || dtype == TVS_F64, TVS_ERR_INVALID_ARG, "bad dtype");
+        TVS_REQUIRE(inner_iters >= 1 && reps >= 1, TVS_ERR_INVALID_ARG, "inner_iters, reps >= 1");
+        TVS_HIP(hipSetDevice(ctx->device));
+        if (dtype == TVS_F32)
+            autotune_batched<float>(ctx, n_slices, slices, inner_iters, reps, best_index,
+                                    ms_per_iter_out);
+        else
+            autotune_batched<double>(ctx, n_slices, slices, inner_iters, reps, best_index,
+                                     ms_per_iter_out);
+        return TVS_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return TVS_ERR_OOM;
+    } catch (...) {
+        set_error("unexpected C++ exception");
+        return TVS_ERR_DEVICE;
+    }
+}
 
 extern "C" tvs_status tvs_proxskip_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
                                            const tvs_slice* slices, const void* b_pool,
@@ -210,14 +335,16 @@ extern "C" tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype,
     }
     const int bytes = dtype == TVS_F32 ? 4 : 8;
     if (index < 0) {
-        ctx->fgp_tuned.erase(fgp_key(0, n_slices, bytes));
+        ctx->fgp_tuned.erase(tune_key(TK_BATCH, n_slices, 0, bytes));
         return TVS_OK;
     }
     FgpConfig c = fgp_variant(index);
-    if (bytes == 8 && c.tile_w == 64 && c.tile_h == 32 && c.steps == 8) {
+    if (find_variant_index(c, bytes) < 0) {
         set_error("variant not compiled for float64");
         return TVS_ERR_UNSUPPORTED;
     }
-    ctx->fgp_tuned[fgp_key(0, n_slices, bytes)] = c;
+    TuneEntry e;
+    e.cfg = c;
+    ctx->fgp_tuned[tune_key(TK_BATCH, n_slices, 0, bytes)] = e;
     return TVS_OK;
 }

@@ -271,15 +271,21 @@ FgpConfig fgp_variant(int index) {
     return c;
 }
 
-static int find_variant(const FgpConfig& c, int dtype_bytes) {
+int find_variant_index(const FgpConfig& c, int dtype_bytes) {
     for (int i = 0; i < fgp_variant_count(); ++i) {
         const FgpVariant& V = kFgpVariants[i];
         if (V.bw == c.tile_w && V.bh == c.tile_h && V.ts == c.steps) {
-            if (dtype_bytes == 8 && V.bw == 64 && V.bh == 32 && V.ts == 8) break;
+            if (dtype_bytes == 8 && V.bw == 64 && V.bh == 32 && V.ts == 8) return -1;
             return i;
         }
     }
-    throw Error{TVS_ERR_UNSUPPORTED, "FGP tile configuration not compiled"};
+    return -1;
+}
+
+static int find_variant(const FgpConfig& c, int dtype_bytes) {
+    const int i = find_variant_index(c, dtype_bytes);
+    if (i < 0) throw Error{TVS_ERR_UNSUPPORTED, "FGP tile configuration not compiled"};
+    return i;
 }
 
 // Runs `iters` FGP iterations; returns the buffer holding the final dual

@@ -60,8 +60,24 @@ struct FgpConfig {
     int tile_w = 32, tile_h = 32, steps = 4;
 };
 
-inline uint64_t fgp_key(int H, int W, int dtype_bytes) {
-    return ((uint64_t)(uint32_t)H << 32) | ((uint64_t)(uint32_t)W << 4) | (uint64_t)dtype_bytes;
+// Autotuner entries: per exact image size, per size class (each side rounded
+// up to a power of two, at least 16) and per batched slice count.
+enum TuneKind : int { TK_IMAGE = 0, TK_CLASS = 1, TK_BATCH = 2 };
+
+struct TuneEntry {
+    FgpConfig cfg;
+    double ms_per_iter = -1.0;  // measured time per FGP iteration, -1 if set by hand
+};
+
+inline uint64_t tune_key(int kind, int a, int b, int dtype_bytes) {
+    return ((uint64_t)(uint32_t)a << 34) | ((uint64_t)(uint32_t)b << 6) |
+           ((uint64_t)(uint32_t)kind << 4) | (uint64_t)(uint32_t)dtype_bytes;
+}
+
+inline int size_class(int x) {
+    int c = 16;
+    while (c < x && c < (1 << 30)) c <<= 1;
+    return c;
 }
 
 }  // namespace tvs
@@ -73,8 +89,9 @@ struct tvs_ctx {
     int n_cu = 0;
     // FGP momentum table: beta[k] for k < beta_len (float and double copies)
     int beta_len = 0;
-    // FGP tile / temporal-depth choice per (H, W, dtype), set by the autotuner
-    std::map<uint64_t, tvs::FgpConfig> fgp_tuned;
+    // FGP tile / temporal-depth choices (tune_key -> entry), set by the
+    // autotuner, by hand or from a tuning file
+    std::map<uint64_t, tvs::TuneEntry> fgp_tuned;
     // cached graphs of solver runs
     std::vector<tvs::GraphEntry*> graphs;
 };
@@ -181,7 +198,11 @@ template <typename T> void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T*
 // FGP on the dual: runs `iters` iterations from the warm dual in q_inout and
 // returns the buffer holding the final dual (q_inout or a scratch buffer);
 // launch_finalize then forms z and copies the dual back into q_inout.
+// FGP configuration for one H x W image: the exact-size entry, else the size
+// class entry, else the default.  fgp_config_batched: per slice count.
 FgpConfig fgp_config(tvs_ctx* ctx, int H, int W, int dtype_bytes);
+FgpConfig fgp_config_batched(tvs_ctx* ctx, int n_slices, int dtype_bytes);
+int find_variant_index(const FgpConfig& c, int dtype_bytes);  // -1 if not compiled
 int fgp_variant_count();
 FgpConfig fgp_variant(int index);
 template <typename T>
