@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--fgp-size", type=int, default=8192)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-prox training and runs")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the per-kernel launches (event times, FGP HBM rate, the copy that "
+                         "calibrates byte counters): the short program to run under rocprofv3 "
+                         "--pmc; prints a kernels record, not the benchmark line")
     return ap.parse_args()
 
 
@@ -82,6 +86,16 @@ def main():
     sigma = tau = 1.0 / Lnorm
     best, _ = T.tvs_fgp_autotune(ctx, T.TVS_F32, N, N, Kin, 3)
     log(f"|A| = {Lnorm:.10f}; FGP tile variant {T.tvs_fgp_variant(best)}")
+
+    if args.kernels_only:
+        kern = kernel_times(T, ctx, op, N, na, nd, Kin, 0, K)
+        fgp_big = fgp_hbm(T, ctx, args.fgp_size, Kin)
+        print(json.dumps({"record": "kernels", "launch_ms": kern["launch_ms"],
+                          "copy_calibration_bytes": COPY_CAL_BYTES, "tv_prox_hbm": fgp_big}),
+              flush=True)
+        T.tvs_op_destroy(op)
+        T.tvs_ctx_destroy(ctx)
+        return
 
     x = torch.zeros(N, N, device=dev)
     h = torch.zeros_like(x)
@@ -239,11 +253,39 @@ def kernel_times(T, ctx, op, N, na, nd, Kin, n_prox, K):
     bp = _evtime(lambda: T.tvs_op_adjoint(op, yi, xo), 50)        # one joseph_adj launch
     fp = _evtime(lambda: T.tvs_op_apply(op, xi, yo), 50)          # transpose + joseph_fwd
     prox = _evtime(lambda: T.tvs_tv_prox(ctx, xi, 0.05, Kin, 1, qq, xo), 20)
+    # a plain device copy of known size (256 MiB each way): the reference that
+    # scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes
+    cal_src = torch.zeros(COPY_CAL_BYTES // 4, device=dev)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
     per_step = {"joseph_adj": bp * K, "joseph_fwd": fp * K, "fgp_prox": prox * n_prox}
     log("kernel ms: " + ", ".join(f"{k} {v:.4f}" for k, v in
                                   (("joseph_adj", bp), ("joseph_fwd", fp), ("fgp_prox", prox))))
     return {"launch_ms": {"joseph_adj": bp, "joseph_fwd": fp, "fgp_prox": prox},
             "per_step_ms": per_step}
+
+
+COPY_CAL_BYTES = 256 << 20
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "joseph_adj_ct512_pmc.md")
+
+
+def measured_traffic(kernel_source, hash_key="source_sha256"):
+    """Bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PMC_SUMMARY).read()
+        m = re.search(r"```json\n(.*?)\n```", text, re.S)
+        rec = json.loads(m.group(1))
+        src = open(os.path.join(ROOT, kernel_source), "rb").read()
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get(hash_key) != hashlib.sha256(src).hexdigest():
+        return None
+    return rec
 
 
 def joseph_nnz(N, na, nd):
@@ -272,9 +314,12 @@ def roofline(dom, kern, N, na, nd, Kin):
         nnz = joseph_nnz(N, na, nd)
         flops = 2.0 * nnz                     # one multiply-add per matrix weight
         ach = flops / (ms * 1e-3) / 1e12
+        rec = measured_traffic("paper_2411_00688_amd/csrc/kernels_ops.hip")
+        key = "joseph_adj_bytes_per_launch" if dom == "joseph_adj" else "joseph_fwd_bytes_per_launch"
+        traffic = rec.get(key) if rec else None
         return {"kernel": dom, "bound": "alu", "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_TFLOPS, 5), "traffic": None,
+                "frac": round(ach / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
                 "launch_ms": round(ms, 5), "work": f"2 flop per weight, {nnz} weights"}
     # FGP prox call: Kin iterations of 28 B/px algorithmic traffic
     byts = 28.0 * N * N * Kin
@@ -309,6 +354,12 @@ def fgp_hbm(T, ctx, n, Kin):
         gbs = 28.0 * n * n * iters / (ms * 1e-3) / 1e9
         res[name] = {"variant": list(T.tvs_fgp_variant(vi)), "ms_per_iter": round(ms / iters, 4),
                      "GB/s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+    # measured bytes per launch (rocprofv3 counters, while the kernel source is unchanged)
+    rec = measured_traffic("paper_2411_00688_amd/csrc/kernels_fgp.hip", "fgp_source_sha256")
+    if rec and n == 8192:
+        res["one_iter_per_launch"]["traffic"] = rec.get("fgp_ts1_8192_bytes_per_launch")
+        if res["tuned"]["variant"] == [64, 16, 4]:
+            res["tuned"]["traffic_per_launch_of_4_iters"] = rec.get("fgp_ts4_8192_bytes_per_launch")
     T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, -1)
     del v, q, z
     torch.cuda.empty_cache()

@@ -63,7 +63,11 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
     constexpr int P = CONV_TILE + 2;               // input patch edge (halo 1)
     constexpr int PST = (CIN == 32) ? 40 : 2;      // LDS pixel stride (bf16)
     constexpr int MB = COUTP / 16;
-    __shared__ __attribute__((aligned(16))) uint16_t s_w[NS][COUTP * WST];
+    // CIN = 32: every wave keeps all its weight fragments in registers for the
+    // block's lifetime (9 taps x MB x NS x 16 bytes); only the activations
+    // go through LDS.  CIN = 2: one K slice, staged once through LDS.
+    constexpr int WS = (CIN == 32) ? 8 : COUTP * WST;
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[NS][WS];
     __shared__ __attribute__((aligned(16))) uint16_t s_x[NS][P * P * PST];
 
     const int tid = threadIdx.x;
@@ -71,13 +75,32 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
     const int nl = lane & 15, g = lane >> 4;
     const int H = a.H, W = a.W;
 
+    bf16x8 wreg[NS][(CIN == 32) ? 9 : 1][MB];
+    if constexpr (CIN == 32) {
 #pragma unroll
-    for (int sp = 0; sp < NS; ++sp) {
-        const uint16_t* src = sp == 0 ? a.wt : a.wt_lo;
-        for (int idx = tid; idx < COUTP * KP / 8; idx += NT) {
-            int row = idx / (KP / 8), c8 = idx % (KP / 8);
-            *(uint4*)&s_w[sp][row * WST + c8 * 8] = *(const uint4*)&src[(size_t)row * KP + c8 * 8];
+        for (int sp = 0; sp < NS; ++sp) {
+            const uint16_t* src = sp == 0 ? a.wt : a.wt_lo;
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+                    wreg[sp][t][m] = as_bf8(*(const uint4*)&src[(size_t)(m * 16 + nl) * KP + t * 32 + g * 8]);
         }
+    } else {
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const uint16_t* src = sp == 0 ? a.wt : a.wt_lo;
+            for (int idx = tid; idx < COUTP * KP / 8; idx += NT) {
+                int row = idx / (KP / 8), c8 = idx % (KP / 8);
+                *(uint4*)&s_w[sp][row * WST + c8 * 8] = *(const uint4*)&src[(size_t)row * KP + c8 * 8];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+                wreg[sp][0][m] = as_bf8(*(const uint4*)&s_w[sp][(m * 16 + nl) * WST + g * 8]);
     }
 
     for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
@@ -129,12 +152,6 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
                 const int dy = t / 3, dx = t % 3;
-                bf16x8 wa[NS][MB];
-#pragma unroll
-                for (int sp = 0; sp < NS; ++sp)
-#pragma unroll
-                    for (int m = 0; m < MB; ++m)
-                        wa[sp][m] = as_bf8(*(const uint4*)&s_w[sp][(m * 16 + nl) * WST + t * 32 + g * 8]);
 #pragma unroll
                 for (int rb = 0; rb < RPW; ++rb) {
                     const int pr = wave * RPW + rb + dy, pc = nl + dx;
@@ -144,22 +161,16 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                         xb[sp] = as_bf8(*(const uint4*)&s_x[sp][(pr * P + pc) * PST + g * 8]);
 #pragma unroll
                     for (int m = 0; m < MB; ++m) {
-                        acc[m][rb] = mfma(wa[0][m], xb[0], acc[m][rb]);
+                        acc[m][rb] = mfma(wreg[0][t][m], xb[0], acc[m][rb]);
                         if (SPLIT) {
-                            acc[m][rb] = mfma(wa[0][m], xb[NS - 1], acc[m][rb]);
-                            acc[m][rb] = mfma(wa[NS - 1][m], xb[0], acc[m][rb]);
+                            acc[m][rb] = mfma(wreg[0][t][m], xb[NS - 1], acc[m][rb]);
+                            acc[m][rb] = mfma(wreg[NS - 1][t][m], xb[0], acc[m][rb]);
                         }
                     }
                 }
             }
         } else {
             // K = (tap, ci) with k = 2 t + ci: lane group g holds taps 4g .. 4g+3
-            bf16x8 wa[NS][MB];
-#pragma unroll
-            for (int sp = 0; sp < NS; ++sp)
-#pragma unroll
-                for (int m = 0; m < MB; ++m)
-                    wa[sp][m] = as_bf8(*(const uint4*)&s_w[sp][(m * 16 + nl) * WST + g * 8]);
 #pragma unroll
             for (int rb = 0; rb < RPW; ++rb) {
                 bf16x8 xb[NS];
@@ -176,10 +187,10 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                 }
 #pragma unroll
                 for (int m = 0; m < MB; ++m) {
-                    acc[m][rb] = mfma(wa[0][m], xb[0], acc[m][rb]);
+                    acc[m][rb] = mfma(wreg[0][0][m], xb[0], acc[m][rb]);
                     if (SPLIT) {
-                        acc[m][rb] = mfma(wa[0][m], xb[NS - 1], acc[m][rb]);
-                        acc[m][rb] = mfma(wa[NS - 1][m], xb[0], acc[m][rb]);
+                        acc[m][rb] = mfma(wreg[0][0][m], xb[NS - 1], acc[m][rb]);
+                        acc[m][rb] = mfma(wreg[NS - 1][0][m], xb[0], acc[m][rb]);
                     }
                 }
             }
@@ -347,13 +358,27 @@ __global__ __launch_bounds__(CONV_NT) void conv3x3_wgrad_kernel(WgradArgs a) {
     }
 }
 
-// fixed-order sum of the per-block partials into the gradient vector
-__global__ void wgrad_reduce_kernel(const float* part, int nblocks, int len, float* out) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= len) return;
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * len + idx];
-    out[idx] = s;
+// Fixed-order sum of the per-block partials into the gradient vector.  A
+// block covers 32 consecutive entries; its 8 thread rows each sum every 8th
+// partial (rows r, r + 8, ...), then the 8 row sums are added in row order.
+constexpr int WR_COLS = 32, WR_ROWS = 8;
+__global__ __launch_bounds__(WR_COLS* WR_ROWS) void wgrad_reduce_kernel(const float* part,
+                                                                      int nblocks, int len,
+                                                                      float* out) {
+    __shared__ float s[WR_ROWS][WR_COLS];
+    const int c = threadIdx.x % WR_COLS, r = threadIdx.x / WR_COLS;
+    const int idx = blockIdx.x * WR_COLS + c;
+    float acc = 0.f;
+    if (idx < len)
+        for (int b = r; b < nblocks; b += WR_ROWS) acc += part[(size_t)b * len + idx];
+    s[r][c] = acc;
+    __syncthreads();
+    if (r == 0 && idx < len) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < WR_ROWS; ++k) t += s[k][c];
+        out[idx] = t;
+    }
 }
 
 // ------------------------------------------------------------------ head
@@ -441,12 +466,19 @@ __global__ void head_bwd_kernel(HeadArgs a) {
     }
 }
 
-__global__ void sum_doubles_kernel(const double* part, int n, double* out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < n; ++b) s += part[b];
-        out[0] = s;
+// Fixed-order sum of n doubles by one block: thread t adds elements t,
+// t + 256, ... in order, then a fixed pairwise tree over the 256 sums.
+__global__ __launch_bounds__(256) void sum_doubles_kernel(const double* part, int n, double* out) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[0] = s[0];
 }
 
 // ------------------------------------------------------------------ optimiser
@@ -532,8 +564,9 @@ void launch_conv(tvs_ctx* ctx, int cin, int coutp, int in_mode, int out_mode, bo
     TVS_REQUIRE(!split || out_mode != OUT_MASK_BF16, TVS_ERR_UNSUPPORTED,
                 "conv3x3: the input-gradient pass is single-part");
     hipStream_t st = ctx->stream;
-    // split blocks use about 90 KB of LDS: one 8-wave block per CU
-    const dim3 grid(grid_for(ctx, a.n_tiles, split ? 1 : 3)), block(split ? 512 : 256);
+    // register-resident weights leave room for two 4-wave blocks (single
+    // part) or one 8-wave block (two parts) per CU
+    const dim3 grid(grid_for(ctx, a.n_tiles, split ? 1 : 2)), block(split ? 512 : 256);
 #define TVS_CONV(CI, CO, IM, OM, SP) conv3x3_kernel<CI, CO, IM, OM, SP><<<grid, block, 0, st>>>(a)
     if (cin == 2 && coutp == 32 && in_mode == IN_VLAM && out_mode == OUT_RELU_BF16) {
         if (split) TVS_CONV(2, 32, IN_VLAM, OUT_RELU_BF16, true);
@@ -585,7 +618,8 @@ void launch_wgrad(tvs_ctx* ctx, int layer, WgradArgs a, float* grad_out) {
             throw Error{TVS_ERR_INVALID_ARG, "wgrad: bad layer"};
     }
     TVS_LAUNCH_CHECK();
-    wgrad_reduce_kernel<<<div_up(len, 256), 256, 0, st>>>(a.part, nblk, len, grad_out);
+    wgrad_reduce_kernel<<<div_up(len, WR_COLS), WR_COLS * WR_ROWS, 0, st>>>(a.part, nblk, len,
+                                                                          grad_out);
     TVS_LAUNCH_CHECK();
 }
 
@@ -599,7 +633,7 @@ void launch_head_fwd(tvs_ctx* ctx, HeadArgs a, int nblk) {
     head_fwd_kernel<<<nblk, 256, 0, ctx->stream>>>(a);
     TVS_LAUNCH_CHECK();
     if (a.z_target) {
-        sum_doubles_kernel<<<1, 64, 0, ctx->stream>>>(a.loss_part, nblk, a.loss_out);
+        sum_doubles_kernel<<<1, 256, 0, ctx->stream>>>(a.loss_part, nblk, a.loss_out);
         TVS_LAUNCH_CHECK();
     }
 }

@@ -187,7 +187,9 @@ __device__ __forceinline__ void fgp_tile(const FgpArgs<T>& a, int ty, int tx) {
 template <typename T, int BW, int BH, int TS>
 __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
     if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
-    fgp_tile<T, BW, BH, TS>(a, (int)blockIdx.y, (int)blockIdx.x);
+    const int gx = div_up(a.W, BW);
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    fgp_tile<T, BW, BH, TS>(a, t / gx, t % gx);
 }
 
 // Batched form: block b of the launch works on tile (b - prefix[i]) of slice
@@ -216,7 +218,7 @@ __device__ __forceinline__ int find_item(const int* prefix, int n, int b) {
 
 template <typename T, int BW, int BH, int TS>
 __global__ __launch_bounds__(256) void fgp_tb_batched_kernel(FgpBatchArgs<T> a) {
-    const int b = (int)blockIdx.x;
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // one block per tile
     const int i = find_item(a.prefix, a.n_act, b);
     const BSlice<T> sl = a.sl[a.act[i]];
     const int t = b - a.prefix[i];
@@ -248,7 +250,7 @@ static const FgpVariant kFgpVariants[] = {
 template <typename T>
 static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     const FgpVariant& V = kFgpVariants[vi];
-    dim3 grid(div_up(a.W, V.bw), div_up(a.H, V.bh));
+    dim3 grid(div_up(a.W, V.bw) * div_up(a.H, V.bh));
 #define TVS_FGPV(BW_, BH_, TS_)                                                            \
     if (V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                       \
         hipLaunchKernelGGL((fgp_tb_kernel<T, BW_, BH_, TS_>), grid, dim3(256), 0, st, a); \

@@ -118,14 +118,15 @@ void launch_transpose(tvs_ctx* ctx, int H, int W, const T* x, T* xT) {
     TVS_LAUNCH_CHECK();
 }
 
-// Writes the 32 x 32 tile of xbar staged in LDS to xbarT, coalesced.
-template <typename T>
+// Writes the 32 x 32 tile of xbar staged in LDS to xbarT, coalesced (NT
+// threads per block).
+template <typename T, int NT = 256>
 __device__ __forceinline__ void store_tile_transposed(T (*s_t)[33], int i0, int j0, int H, int W,
                                                       T* xT, int ldT) {
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < 1024 / NT; ++p) {
+        const int idx = (int)threadIdx.x + p * NT;
         const int jj = idx / 32, ii = idx % 32;
         if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * ldT + i0 + ii] = s_t[ii][jj];
     }
@@ -777,9 +778,12 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     __shared__ int wst[RD_MAXA];
     __shared__ float2 line[4][64];
     __shared__ float tileT[RD_P][RD_P + 1];
-    const int G = a.groups, g = (int)blockIdx.y;
-    const int tiles_x = div_up(a.W, RD_P);
-    const int i0 = ((int)blockIdx.x / tiles_x) * RD_P, j0 = ((int)blockIdx.x % tiles_x) * RD_P;
+    // block -> (angle group, tile), each XCD taking a contiguous range so that
+    // the blocks sharing a group's sinogram rows share one L2
+    const int tiles_x = div_up(a.W, RD_P), tiles = tiles_x * div_up(a.H, RD_P);
+    const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int G = a.groups, g = L / tiles, tl = L - (L / tiles) * tiles;
+    const int i0 = (tl / tiles_x) * RD_P, j0 = (tl % tiles_x) * RD_P;
     const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int na_g = (a.n_ang - g + G - 1) / G;
     for (int m = tid; m < na_g; m += 256) wst[m] = rd_window(a.ang[g + m * G], i0, j0);
@@ -818,28 +822,26 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
 // Sums the G partial images in order and applies the backprojector epilogue
 // (store, or the data step with the transposed xbar copy).  32 x 32 tiles.
 template <typename T>
-__global__ __launch_bounds__(256) void joseph_adj_sum_kernel(const T* part, int G, int H, int W,
-                                                             T* x_out, PrimalStep<T> ps, int has_ps) {
+__global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int G, int H, int W,
+                                                              T* x_out, PrimalStep<T> ps, int has_ps) {
+    // one thread per pixel of a 32 x 32 tile: 16 waves per block keep the
+    // G independent partial loads of many pixels in flight
     __shared__ T s_t[32][33];
     const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
     const size_t plane = (size_t)H * W;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
-        const int li = idx / 32, lj = idx % 32;
-        const int i = i0 + li, j = j0 + lj;
-        if (i < H && j < W) {
-            const size_t gi = (size_t)i * W + j;
-            T s = part[gi];
-            for (int k = 1; k < G; ++k) s += part[(size_t)k * plane + gi];
-            if (has_ps)
-                s_t[li][lj] = primal_step(ps, gi, i, j, s);
-            else
-                x_out[gi] = s;
-        }
+    const int li = (int)threadIdx.x / 32, lj = (int)threadIdx.x % 32;
+    const int i = i0 + li, j = j0 + lj;
+    if (i < H && j < W) {
+        const size_t gi = (size_t)i * W + j;
+        T s = part[gi];
+        for (int k = 1; k < G; ++k) s += part[(size_t)k * plane + gi];
+        if (has_ps)
+            s_t[li][lj] = primal_step(ps, gi, i, j, s);
+        else
+            x_out[gi] = s;
     }
     if (has_ps && ps.pdhg && !ps.theta && ps.xbarT)
-        store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
+        store_tile_transposed<T, 1024>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
 }
 
 // Angle groups of the ray-driven backprojector: enough blocks for two per
@@ -883,10 +885,10 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
             r.W = a.W;
             r.n_det = a.n_det;
             r.part = part;
-            hipLaunchKernelGGL(joseph_adj_rd_kernel, dim3(tiles, G), dim3(256), 0, ctx->stream, r);
+            hipLaunchKernelGGL(joseph_adj_rd_kernel, dim3(tiles * G), dim3(256), 0, ctx->stream, r);
             TVS_LAUNCH_CHECK();
             hipLaunchKernelGGL((joseph_adj_sum_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)),
-                               dim3(256), 0, ctx->stream, (const T*)part, G, a.H, a.W, x_out, a.ps,
+                               dim3(1024), 0, ctx->stream, (const T*)part, G, a.H, a.W, x_out, a.ps,
                                a.has_ps);
             TVS_LAUNCH_CHECK();
             return;

@@ -417,4 +417,16 @@ float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam,
 
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// The GPU deals workgroups to its 8 XCDs (each with its own L2) round-robin
+// by linear workgroup id.  For a 1-D launch of n_tiles workgroups this maps
+// workgroup L to a tile so that each XCD works through one contiguous range
+// of tiles (row-major), and tiles that share halo cache lines meet in the
+// same L2.  A bijection on [0, n_tiles).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int L, int n_tiles) {
+    const int x = L % kXcds, k = L / kXcds;
+    const int base = n_tiles / kXcds, rem = n_tiles % kXcds;
+    return x * base + (x < rem ? x : rem) + k;
+}
+
 }  // namespace tvs
