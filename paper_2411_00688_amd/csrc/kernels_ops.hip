@@ -414,13 +414,16 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
             // 32.32 fixed point: U = Aq d + Bq s + Cq exactly, floor(u) is the
             // high word and the fraction the low word.
             long long U = g.Aqi * (long long)d + g.Cqi + g.Bqi * (long long)lo;
-#pragma unroll 4
+#pragma unroll 8
             for (int s = lo; s < hi; ++s) {
                 const int j0 = (int)(U >> 32);
                 const T f = (T)(unsigned)U * 2.3283064365386963e-10f;
-                const T v0 = row[j0], v1 = row[j0 + 1];
-                acc += (T(1) - f) * v0;
-                acc += f * v1;
+                // both neighbours in one 8-byte load (4-byte aligned, inside the
+                // padded row)
+                float2 v;
+                __builtin_memcpy(&v, row + j0, sizeof(v));
+                acc += (T(1) - f) * v.x;
+                acc += f * v.y;
                 U += g.Bqi;
                 row += ld;
             }
@@ -730,31 +733,43 @@ __device__ __forceinline__ int rd_window(const JAngle& g, int i0, int j0) {
     return (int)floor(fmin(fmin(e1, e2), fmin(e3, e4))) - 3;
 }
 
-// One angle for the wavefront's RD_L steps s_first .. s_first + RD_L - 1 and
-// the tile's pixels t0 .. t0 + RD_P - 1 along the interpolation axis.  The
-// LDS line has 64 float2 slots: slot 2 + p is pixel p; slots 0, 1 and 62, 63
-// absorb samples outside the tile (clamped there), so every lane writes
-// unconditionally.  .x collects (1 - f) y of the ray whose sample floors to
-// the pixel, .y collects f y of the ray that floors to the pixel before.
-__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, int ws, int s_first,
-                                         int t0, int n_step, int lane, float2* ln,
-                                         float (&acc)[RD_L]) {
+// First ray of the 64-ray window of angle gg at step s: the ray index e at
+// which the sample reaches the near edge of the tile's pixel range (the
+// smaller of the two edges' ray indices), minus one.  Within +-1 of this
+// value the window still covers every ray that touches the tile (rays are at
+// least one pixel apart, a tile row needs at most 62 of them), so its float64
+// rounding does not matter.
+__device__ __forceinline__ int rd_first_ray(const JAngle& gg, int s, int t0) {
+    const double Kr = fma(gg.B, (double)s, gg.C);
+    const double e = fmin(((double)(t0 - 1) - Kr) * gg.inv_A, ((double)(t0 + RD_P) - Kr) * gg.inv_A);
+    return (int)floor(e) - 1;
+}
+
+// One angle for the wavefront's RD_L steps (rows q = RD_L w + r of the tile's
+// step range) and the tile's pixels t0 .. t0 + RD_P - 1 along the
+// interpolation axis.  Per step the block-wide tables give the window's first
+// ray relative to the staged sinogram window (btab) and its exact 32.32
+// position Aq d0 + Bq s + Cq (utab); lane l takes ray d0 + l, whose position
+// is utab + l Aq, the same integer the projector forms, so the scatter is the
+// exact transpose of the projector.  The LDS line has 64 float2 slots: slot
+// 2 + p is pixel p; slots 0, 1 and 62, 63 absorb samples outside the tile
+// (clamped there), so every lane writes unconditionally.  .x collects
+// (1 - f) y of the ray whose sample floors to the pixel, .y collects f y of
+// the ray that floors to the pixel before.
+__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, const int* btab,
+                                         const long long* utab, int q0, int s_first, int t0,
+                                         int n_step, int lane, float2* ln, float (&acc)[RD_L]) {
     const float wgt = (float)gg.wgt;
-    double K = fma(gg.Bq, (double)s_first, gg.Cq);
-    const double Kr0 = fma(gg.B, (double)s_first, gg.C);
-    double e = fmin(((double)(t0 - 1) - Kr0) * gg.inv_A, ((double)(t0 + RD_P) - Kr0) * gg.inv_A);
-    const double de = -gg.B * gg.inv_A;
-    const double AqL = gg.Aq * (double)lane;
+    const long long AqL = gg.Aqi * (long long)lane;
 #pragma unroll
     for (int r = 0; r < RD_L; ++r) {
         if (s_first + r < n_step) {
-            const int dfirst = (int)floor(e) - 1;
-            int bi = dfirst - ws + lane;
+            int bi = btab[q0 + r] + lane;
             bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
             const float val = wgt * ys[bi];
-            int jj;
-            float f;
-            fx_split(fma(gg.Aq, (double)dfirst, K) + AqL, jj, f);
+            const long long U = utab[q0 + r] + AqL;
+            const int jj = (int)(U >> 32);
+            const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
             int lt = jj - t0;
             lt = lt < -2 ? -2 : (lt > RD_P ? RD_P : lt);
             ln[lane] = make_float2(0.0f, 0.0f);
@@ -768,14 +783,14 @@ __device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, int 
             }
             __asm__ __volatile__("" ::: "memory");
         }
-        K += gg.Bq;
-        e += de;
     }
 }
 
 __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
     __shared__ float yS[RD_MAXA][RD_NB];
     __shared__ int wst[RD_MAXA];
+    __shared__ int btab[RD_MAXA][RD_P];
+    __shared__ long long utab[RD_MAXA][RD_P];
     __shared__ float2 line[4][64];
     __shared__ float tileT[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
@@ -793,6 +808,15 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
         const int d = wst[m] + bb;
         yS[m][bb] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
     }
+    // per (angle, step) window tables
+    for (int idx = tid; idx < na_g * RD_P; idx += 256) {
+        const int m = idx / RD_P, q = idx - m * RD_P;
+        const JAngle gg = a.ang[g + m * G];
+        const int s = (gg.cls ? j0 : i0) + q, t0 = gg.cls ? i0 : j0;
+        const int d0 = rd_first_ray(gg, s, t0);
+        btab[m][q] = d0 - wst[m];
+        utab[m][q] = gg.Aqi * (long long)d0 + gg.Bqi * (long long)s + gg.Cqi;
+    }
     __syncthreads();
     float accR[RD_L], accC[RD_L];
 #pragma unroll
@@ -800,9 +824,11 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     for (int m = 0; m < na_g; ++m) {
         const JAngle gg = a.ang[g + m * G];
         if (gg.cls == 0)
-            rd_angle(gg, yS[m], wst[m], i0 + RD_L * w, j0, a.H, lane, line[w], accR);
+            rd_angle(gg, yS[m], btab[m], utab[m], RD_L * w, i0 + RD_L * w, j0, a.H, lane, line[w],
+                     accR);
         else
-            rd_angle(gg, yS[m], wst[m], j0 + RD_L * w, i0, a.W, lane, line[w], accC);
+            rd_angle(gg, yS[m], btab[m], utab[m], RD_L * w, j0 + RD_L * w, i0, a.W, lane, line[w],
+                     accC);
     }
     // column-stepping sums are held per (row = lane, column = 15 w + c): transpose
     if (lane < RD_P) {
