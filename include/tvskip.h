@@ -90,9 +90,15 @@ tvs_status tvs_op_blur_periodic(tvs_ctx* ctx, int H, int W, const double* kernel
  *   A ray with |cos t| >= |sin t| is sampled once per image row, otherwise
  *   once per column, interpolating linearly between the two nearest pixel
  *   centres of that row (column), weighted by pixel / max(|cos t|, |sin t|).
- * The adjoint is its exact transpose (same interpolation weights), computed
- * by a gather over pixels without atomics.  angles_host: n_ang radians.
- * Requires det_spacing >= pixel / 4. */
+ * The adjoint is its exact transpose (same interpolation weights), without
+ * atomics: for float32 with det_spacing >= pixel / max(|cos t|, |sin t|)
+ * over all angles (so neighbouring rays are at least one pixel apart), a
+ * ray-driven scatter into LDS tiles plus a fixed-order sum of per-angle-group
+ * partial images; otherwise (and for float64) a gather over pixels.  In
+ * float32 the ray positions are 32.32 fixed-point integers shared by both
+ * directions, so the transpose is exact there too.  angles_host: n_ang
+ * radians.  Requires pixel / 4 <= det_spacing <= 4 pixel, 1 <= n_ang <= 65535
+ * and n_det, H, W <= 32768 (TVS_ERR_SHAPE / TVS_ERR_INVALID_ARG otherwise). */
 tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
                             const double* angles_host, int n_det, double pixel,
                             double det_spacing, tvs_op** out);

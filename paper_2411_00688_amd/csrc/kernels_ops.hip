@@ -733,65 +733,96 @@ __device__ __forceinline__ int rd_window(const JAngle& g, int i0, int j0) {
     return (int)floor(fmin(fmin(e1, e2), fmin(e3, e4))) - 3;
 }
 
-// First ray of the 64-ray window of angle gg at step s: the ray index e at
-// which the sample reaches the near edge of the tile's pixel range (the
-// smaller of the two edges' ray indices), minus one.  Within +-1 of this
-// value the window still covers every ray that touches the tile (rays are at
-// least one pixel apart, a tile row needs at most 62 of them), so its float64
-// rounding does not matter.
-__device__ __forceinline__ int rd_first_ray(const JAngle& gg, int s, int t0) {
-    const double Kr = fma(gg.B, (double)s, gg.C);
-    const double e = fmin(((double)(t0 - 1) - Kr) * gg.inv_A, ((double)(t0 + RD_P) - Kr) * gg.inv_A);
-    return (int)floor(e) - 1;
+// A value every lane of the wavefront holds, moved to scalar registers.
+__device__ __forceinline__ long long wave_uniform64(long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-// One angle for the wavefront's RD_L steps (rows q = RD_L w + r of the tile's
-// step range) and the tile's pixels t0 .. t0 + RD_P - 1 along the
-// interpolation axis.  Per step the block-wide tables give the window's first
-// ray relative to the staged sinogram window (btab) and its exact 32.32
-// position Aq d0 + Bq s + Cq (utab); lane l takes ray d0 + l, whose position
-// is utab + l Aq, the same integer the projector forms, so the scatter is the
-// exact transpose of the projector.  The LDS line has 64 float2 slots: slot
-// 2 + p is pixel p; slots 0, 1 and 62, 63 absorb samples outside the tile
-// (clamped there), so every lane writes unconditionally.  .x collects
-// (1 - f) y of the ray whose sample floors to the pixel, .y collects f y of
-// the ray that floors to the pixel before.
-__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, const int* btab,
-                                         const long long* utab, int q0, int s_first, int t0,
-                                         int n_step, int lane, float2* ln, float (&acc)[RD_L]) {
+// Index of the ray whose sample reaches the near edge of the tile's pixel
+// range at step s (the smaller of the two edges' ray indices, real-valued).
+// The 64-ray window of a step starts one ray before it; within +-1 of that
+// start the window still covers every ray that touches the tile (rays are at
+// least one pixel apart, a tile row needs at most 62 of them), so rounding
+// in this value does not matter.
+__device__ __forceinline__ double rd_edge_ray(const JAngle& gg, int s, int t0) {
+    const double Kr = fma(gg.B, (double)s, gg.C);
+    return fmin(((double)(t0 - 1) - Kr) * gg.inv_A, ((double)(t0 + RD_P) - Kr) * gg.inv_A);
+}
+
+// One angle for the wavefront's RD_L steps s_first .. s_first + RD_L - 1 and
+// the tile's pixels t0 .. t0 + RD_P - 1 along the interpolation axis.  The
+// window start d0 and its exact 32.32 position Aq d0 + Bq s + Cq are
+// wave-uniform and advance by integer additions per step (scalar unit); lane
+// l takes ray d0 + l at position + l Aq, the same integer the projector forms,
+// so the scatter is the exact transpose of the projector.  Each LDS line is
+// two float arrays of 64 slots (slot 2 + p is pixel p; slots 0, 1 and 62, 63
+// absorb samples outside the tile, clamped there, so every lane writes
+// unconditionally): lx collects (1 - f) y of the ray whose sample floors to
+// the pixel, ly collects f y of the ray that floors to the pixel before.
+// Distinct rays land on distinct slots, so both scatters are free of bank
+// conflicts.  RD_B steps go through RD_B lines at once, so the LDS round
+// trips of a batch overlap; the compiler barriers keep the clear, scatter and
+// gather phases in order across lanes (the lanes of a wavefront exchange
+// data through the line, which per-lane alias analysis does not see).
+static constexpr int RD_B = 1;  // steps per batch (5 measured slower: more LDS per wave, lower occupancy)
+static_assert(RD_L % RD_B == 0, "batches must tile the wavefront's steps");
+
+__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, int ws, int s_first,
+                                         int t0, int n_step, int lane, float* ln,
+                                         float (&acc)[RD_L]) {
     const float wgt = (float)gg.wgt;
     const long long AqL = gg.Aqi * (long long)lane;
+    // window start in 32.32 fixed point: E(s) = E0 + (s - s_first) dE
+    const double e0 = rd_edge_ray(gg, s_first, t0);
+    const double de = -gg.B * gg.inv_A;
+    long long E = wave_uniform64((long long)llrint(ldexp(e0, 32)));
+    const long long dE = wave_uniform64((long long)llrint(ldexp(de, 32)));
+    long long K = wave_uniform64(gg.Bqi * (long long)s_first + gg.Cqi);
 #pragma unroll
-    for (int r = 0; r < RD_L; ++r) {
-        if (s_first + r < n_step) {
-            int bi = btab[q0 + r] + lane;
+    for (int b0 = 0; b0 < RD_L; b0 += RD_B) {
+        float val[RD_B], f[RD_B];
+        int lt[RD_B];
+#pragma unroll
+        for (int k = 0; k < RD_B; ++k) {
+            const int d0 = (int)(E >> 32) - 1;
+            int bi = d0 - ws + lane;
             bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
-            const float val = wgt * ys[bi];
-            const long long U = utab[q0 + r] + AqL;
-            const int jj = (int)(U >> 32);
-            const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
-            int lt = jj - t0;
-            lt = lt < -2 ? -2 : (lt > RD_P ? RD_P : lt);
-            ln[lane] = make_float2(0.0f, 0.0f);
-            __asm__ __volatile__("" ::: "memory");
-            ln[lt + 2].x = (1.0f - f) * val;
-            ln[lt + 3].y = f * val;
-            __asm__ __volatile__("" ::: "memory");
-            if (lane < RD_P) {
-                const float2 v = ln[lane + 2];
-                acc[r] += v.x + v.y;
-            }
-            __asm__ __volatile__("" ::: "memory");
+            val[k] = wgt * ys[bi];
+            const long long U = gg.Aqi * (long long)d0 + K + AqL;
+            f[k] = (float)(unsigned)U * 2.3283064365386963e-10f;
+            const int l = (int)(U >> 32) - t0;
+            lt[k] = l < -2 ? -2 : (l > RD_P ? RD_P : l);
+            E += dE;
+            K += gg.Bqi;
         }
+#pragma unroll
+        for (int k = 0; k < RD_B; ++k)
+            reinterpret_cast<float2*>(ln + 128 * k)[lane] = make_float2(0.0f, 0.0f);
+        __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < RD_B; ++k) {
+            if (s_first + b0 + k < n_step) {
+                ln[128 * k + lt[k] + 2] = (1.0f - f[k]) * val[k];
+                ln[128 * k + 64 + lt[k] + 3] = f[k] * val[k];
+            }
+        }
+        __asm__ __volatile__("" ::: "memory");
+        if (lane < RD_P) {
+#pragma unroll
+            for (int k = 0; k < RD_B; ++k)
+                if (s_first + b0 + k < n_step)
+                    acc[b0 + k] += ln[128 * k + lane + 2] + ln[128 * k + 64 + lane + 2];
+        }
+        __asm__ __volatile__("" ::: "memory");
     }
 }
 
 __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
     __shared__ float yS[RD_MAXA][RD_NB];
     __shared__ int wst[RD_MAXA];
-    __shared__ int btab[RD_MAXA][RD_P];
-    __shared__ long long utab[RD_MAXA][RD_P];
-    __shared__ float2 line[4][64];
+    __shared__ __attribute__((aligned(16))) float line[4][RD_B * 128];
     __shared__ float tileT[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
@@ -799,7 +830,8 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int G = a.groups, g = L / tiles, tl = L - (L / tiles) * tiles;
     const int i0 = (tl / tiles_x) * RD_P, j0 = (tl % tiles_x) * RD_P;
-    const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int na_g = (a.n_ang - g + G - 1) / G;
     for (int m = tid; m < na_g; m += 256) wst[m] = rd_window(a.ang[g + m * G], i0, j0);
     __syncthreads();
@@ -808,27 +840,17 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
         const int d = wst[m] + bb;
         yS[m][bb] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
     }
-    // per (angle, step) window tables
-    for (int idx = tid; idx < na_g * RD_P; idx += 256) {
-        const int m = idx / RD_P, q = idx - m * RD_P;
-        const JAngle gg = a.ang[g + m * G];
-        const int s = (gg.cls ? j0 : i0) + q, t0 = gg.cls ? i0 : j0;
-        const int d0 = rd_first_ray(gg, s, t0);
-        btab[m][q] = d0 - wst[m];
-        utab[m][q] = gg.Aqi * (long long)d0 + gg.Bqi * (long long)s + gg.Cqi;
-    }
     __syncthreads();
     float accR[RD_L], accC[RD_L];
 #pragma unroll
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
     for (int m = 0; m < na_g; ++m) {
         const JAngle gg = a.ang[g + m * G];
+        const int ws = __builtin_amdgcn_readfirstlane(wst[m]);
         if (gg.cls == 0)
-            rd_angle(gg, yS[m], btab[m], utab[m], RD_L * w, i0 + RD_L * w, j0, a.H, lane, line[w],
-                     accR);
+            rd_angle(gg, yS[m], ws, i0 + RD_L * w, j0, a.H, lane, line[w], accR);
         else
-            rd_angle(gg, yS[m], btab[m], utab[m], RD_L * w, j0 + RD_L * w, i0, a.W, lane, line[w],
-                     accC);
+            rd_angle(gg, yS[m], ws, j0 + RD_L * w, i0, a.W, lane, line[w], accC);
     }
     // column-stepping sums are held per (row = lane, column = 15 w + c): transpose
     if (lane < RD_P) {
