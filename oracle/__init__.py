@@ -20,6 +20,11 @@ Parity status of each function (what pins it lives in tests/test_oracle_*.py):
   op_norm ......................... pinned (identity, blur = 1, SVD of small A)
   pdhg_explicit ................... pinned (agrees with PGD/PDHG minimisers and
                                      with the exact 1-D/2-pixel solutions)
+  dual_rof_proxskip ............... pinned (p = 1 equals the separately written
+                                     ProjGD bitwise; 2-pixel closed forms of
+                                     Dual-ROF and Dual-Huber-ROF; the primal
+                                     iterate reaches the TV prox, 1-D taut
+                                     string; duality gap -> 0)
   cnn_forward ..................... pinned (layers against scipy correlate2d,
                                      head closed form with zero weights)
   cnn_loss_grad ................... pinned (central finite differences)
@@ -93,6 +98,12 @@ def lib():
         L.orc_op_norm.restype = C.c_double
         L.orc_pdhg_explicit.argtypes = [C.POINTER(OrcOp), dp, C.c_double, C.c_int, C.c_int64,
                                         dp, dp, dp, C.c_int64, dp]
+        L.orc_dual_rof_proxskip.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double,
+                                            C.c_double, C.c_double, C.c_int64, C.c_uint64,
+                                            C.c_uint64, C.c_int64, dp, dp, u8p, dp, dp]
+        L.orc_dual_rof_proxskip.restype = C.c_int64
+        L.orc_dual_rof_projgd.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double,
+                                          C.c_double, C.c_int64, dp]
         L.orc_cnn_param_count.argtypes = []
         L.orc_cnn_param_count.restype = C.c_size_t
         L.orc_cnn_forward.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
@@ -305,6 +316,35 @@ def pdhg_explicit(A: Op, b, alpha, nonneg, iters, x=None, y1=None, y2=None, obj_
     lib().orc_pdhg_explicit(C.byref(A.s), _p(b), float(alpha), int(nonneg), int(iters),
                             _p(x), _p(y1), _p(y2), int(obj_every), _p(obj))
     return dict(x=x, y1=y1, y2=y2, obj=obj[:nrec])
+
+
+# ---------------------------------------------------------------- light prox (Sec. 2)
+def dual_rof_proxskip(b, alpha, eps, gamma, p, K, seed=0, stream=0, k0=0, q=None, h=None,
+                      u_ref=None):
+    """ProxSkip on Dual-ROF (eps = 0) / Dual-Huber-ROF.  Returns dict(q, h,
+    u = b + div q, theta, nprox, err)."""
+    b = _f64(b)
+    H, W = b.shape
+    q = _state(q, (2, H, W))
+    h = _state(h, (2, H, W))
+    theta = np.zeros(max(K, 1), dtype=np.uint8)
+    err = np.zeros(max(K, 1)) if u_ref is not None else None
+    ur = None if u_ref is None else _f64(u_ref)
+    n = lib().orc_dual_rof_proxskip(H, W, _p(b), float(alpha), float(eps), float(gamma),
+                                    float(p), int(K), int(seed), int(stream), int(k0), _p(q),
+                                    _p(h), theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                    _p(ur) if ur is not None else None,
+                                    _p(err) if err is not None else None)
+    return dict(q=q, h=h, u=b + div(q), theta=theta[:K], nprox=int(n),
+                err=None if err is None else err[:K])
+
+
+def dual_rof_projgd(b, alpha, eps, gamma, K, q=None):
+    b = _f64(b)
+    H, W = b.shape
+    q = _state(q, (2, H, W))
+    lib().orc_dual_rof_projgd(H, W, _p(b), float(alpha), float(eps), float(gamma), int(K), _p(q))
+    return dict(q=q, u=b + div(q))
 
 
 # ---------------------------------------------------------------- learned prox

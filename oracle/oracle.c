@@ -635,3 +635,89 @@ void orc_pdhg_explicit(const orc_op* A, const double* b, double alpha,
     free(T); free(S1); free(ones_n); free(ones_m); free(tmp_n); free(tmp_m);
     free(xn); free(xbar); free(g);
 }
+
+/* ------------------------------------------------------------------------
+ * The light-prox problems of Sec. 2.1-2.2: the dual of TV denoising
+ * (Dual-ROF, and with eps > 0 the Dual-Huber-ROF of Sec. 2.2),
+ *   min_{|q_i| <= alpha} F(q) = 1/2 |div q + b|^2 (+ eps / (2 alpha) |q|^2),
+ * whose gradient is grad F(q) = -D(div q + b) + (eps / alpha) q and whose
+ * nonsmooth part is the indicator of the alpha-ball set C, with prox the
+ * projection P_C of eq. (7) (reading: the projection onto the alpha-ball).
+ * The primal iterate is u_k = b + div q_k.
+ * ------------------------------------------------------------------------ */
+static void dual_rof_grad(int H, int W, const double* b, double alpha, double eps,
+                          const double* q, double* u, double* g) {
+    size_t n = (size_t)H * W;
+    orc_div(H, W, q, u);
+    for (size_t i = 0; i < n; ++i) u[i] += b[i];
+    orc_grad(H, W, u, g);
+    double mu = alpha > 0 ? eps / alpha : 0.0;
+    for (size_t i = 0; i < 2 * n; ++i) g[i] = -g[i] + mu * q[i];
+}
+
+/* ProxSkip (Alg. "ProxSkip") with f = F, psi = indicator of C: the prox of
+ * (gamma / p) psi is P_C whatever the scale.  q, h ([2][H][W]) are in/out;
+ * err_trace (nullable, K values) gets |u_{k+1} - u_ref| / |u_ref| when u_ref
+ * is given.  The prox argument is formed as w + (gamma - gamma / p) h with
+ * w = q - gamma grad F(q), so p = 1 reproduces ProjGD bitwise.  Returns the
+ * number of projections. */
+int64_t orc_dual_rof_proxskip(int H, int W, const double* b, double alpha, double eps,
+                              double gamma, double p, int64_t K, uint64_t seed,
+                              uint64_t stream, int64_t k0, double* q, double* h,
+                              uint8_t* theta_trace, const double* u_ref, double* err_trace) {
+    size_t n = (size_t)H * W;
+    double* u = dalloc(n);
+    double* g = dalloc(2 * n);
+    double* qhat = dalloc(2 * n);
+    double* v = dalloc(2 * n);
+    double coef = gamma - gamma / p, rate = p / gamma;
+    double nref = 0.0;
+    if (u_ref)
+        for (size_t i = 0; i < n; ++i) nref += u_ref[i] * u_ref[i];
+    nref = sqrt(nref);
+    int64_t nprox = 0;
+    for (int64_t kk = 0; kk < K; ++kk) {
+        dual_rof_grad(H, W, b, alpha, eps, q, u, g);
+        int th = orc_coin(seed, stream, k0 + kk, p);
+        for (size_t i = 0; i < 2 * n; ++i) {
+            double w = q[i] - gamma * g[i];
+            qhat[i] = w + gamma * h[i];
+            v[i] = w + coef * h[i];
+        }
+        if (th) {
+            orc_proj_ball(n, v, alpha, q);
+            for (size_t i = 0; i < 2 * n; ++i) h[i] = h[i] + rate * (q[i] - qhat[i]);
+            ++nprox;
+        } else {
+            memcpy(q, qhat, 2 * n * sizeof(double));
+        }
+        if (theta_trace) theta_trace[kk] = (uint8_t)th;
+        if (err_trace && u_ref) {
+            orc_div(H, W, q, u);
+            double e = 0.0;
+            for (size_t i = 0; i < n; ++i) {
+                double d = b[i] + u[i] - u_ref[i];
+                e += d * d;
+            }
+            err_trace[kk] = sqrt(e) / nref;
+        }
+    }
+    free(u); free(g); free(qhat); free(v);
+    return nprox;
+}
+
+/* ProjGD (Chambolle's projected gradient, Sec. 2.1), written separately:
+ *   q_{k+1} = P_C(q_k + gamma (D(div q_k + b) - (eps / alpha) q_k)). */
+void orc_dual_rof_projgd(int H, int W, const double* b, double alpha, double eps, double gamma,
+                         int64_t K, double* q) {
+    size_t n = (size_t)H * W;
+    double* u = dalloc(n);
+    double* g = dalloc(2 * n);
+    double* t = dalloc(2 * n);
+    for (int64_t k = 0; k < K; ++k) {
+        dual_rof_grad(H, W, b, alpha, eps, q, u, g);
+        for (size_t i = 0; i < 2 * n; ++i) t[i] = q[i] - gamma * g[i];
+        orc_proj_ball(n, t, alpha, q);
+    }
+    free(u); free(g); free(t);
+}

@@ -100,6 +100,15 @@ void orc_pdhg_explicit(const orc_op* A, const double* b, double alpha,
                        int nonneg, int64_t iters, double* x, double* y1,
                        double* y2, int64_t obj_every, double* obj_trace);
 
+/* ---- light-prox problems (Sec. 2.1-2.2): ProxSkip on Dual-ROF and
+ * Dual-Huber-ROF (eps > 0), and ProjGD written separately ---- */
+int64_t orc_dual_rof_proxskip(int H, int W, const double* b, double alpha, double eps,
+                              double gamma, double p, int64_t K, uint64_t seed,
+                              uint64_t stream, int64_t k0, double* q, double* h,
+                              uint8_t* theta_trace, const double* u_ref, double* err_trace);
+void orc_dual_rof_projgd(int H, int W, const double* b, double alpha, double eps, double gamma,
+                         int64_t K, double* q);
+
 /* ---- learned TV prox (cnn.c): 2 -> 32 -> 32 -> 32 -> 2, 3x3, dual output ---- */
 #define ORC_CNN_LAYERS 4
 size_t orc_cnn_param_count(void);
