@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--fgp-size", type=int, default=8192)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-prox training and runs")
+    ap.add_argument("--no-light", action="store_true", help="skip the Dual-ROF / Huber runs")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel launches (event times, FGP HBM rate, the copy that "
                          "calibrates byte counters): the short program to run under rocprofv3 "
@@ -145,6 +146,11 @@ def main():
     if not args.no_batched:
         batched = batched_bench(T, ctx)
 
+    # ---- light-prox problems (Dual-ROF / Dual-Huber-ROF, 200 x 300)
+    light = None
+    if not args.no_light:
+        light = light_prox_bench(T, ctx)
+
     # ---- learned prox: trained here on the method's own prox inputs
     learned_res = None
     if not args.no_learned:
@@ -181,6 +187,7 @@ def main():
         "tv_prox_hbm": fgp_big,
         "batched": batched,
         "learned": learned_res,
+        "light_prox": light,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -364,6 +371,74 @@ def fgp_hbm(T, ctx, n, Kin):
     del v, q, z
     torch.cuda.empty_cache()
     log(f"FGP {n}^2: {res}")
+    return res
+
+
+def light_prox_bench(T, ctx, chunk=500, max_iters=50000, tol=1e-5):
+    """ProxSkip on the light-prox problems (Sec. 2.1-2.2) on a 200 x 300
+    shapes-like phantom with noise 0.05, float64.  Dual-ROF (alpha 0.5, step
+    1/8): for p in {1 (ProjGD), 0.5, 0.3, 0.1, 0.01}, the first chunk of
+    `chunk` iterations after which the TV-prox relative duality gap of q is
+    <= tol (a certificate: no reference solution needed), then the time of an
+    un-instrumented run of that many iterations.  Dual-Huber-ROF (alpha 0.55,
+    eps 0.01, p 0.04767, 5000 iterations): throughput and projections."""
+    import numpy as np
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    H, W = 200, 300
+    u, eta = synth.phantom_and_noise(H, W, 12, synth.phantom_seed(5), (H, W))
+    b = torch.tensor(u + 0.05 * eta, dtype=torch.float64, device=dev)
+    q = torch.zeros(2, H, W, dtype=torch.float64, device=dev)
+    hh = torch.zeros_like(q)
+    res = {"image": [H, W], "dtype": "f64", "gap_tol": tol, "dual_rof": {}}
+
+    def reset():
+        q.zero_()
+        hh.zero_()
+
+    for p in (1.0, 0.5, 0.3, 0.1, 0.01):
+        reset()
+        k_hit, nprox = None, 0
+        for k0 in range(0, max_iters, chunk):
+            r = T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, chunk, seed=17, k0=k0)
+            nprox += r["n_prox"]
+            gap, primal = T.tvs_tv_gap(ctx, b, 0.5, 0, q)
+            if gap / primal <= tol:
+                k_hit = k0 + chunk
+                break
+        entry = {"iters": k_hit, "prox_calls": nprox if k_hit else None}
+        if k_hit:
+            reset()
+            T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, k_hit, seed=17, graph=True)
+            reset()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, k_hit, seed=17, graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            entry["ms"] = round(e0.elapsed_time(e1), 3)
+            entry["us_per_iter"] = round(1e3 * e0.elapsed_time(e1) / k_hit, 3)
+        res["dual_rof"][f"p={p}"] = entry
+        log(f"Dual-ROF p={p}: {entry}")
+    # Dual-Huber-ROF at the paper's p (Sec. 2.2)
+    alpha, eps, p, K = 0.55, 0.01, 0.04767, 5000
+    step = 1.0 / (8.0 + eps / alpha)
+    reset()
+    T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K, seed=19, graph=True)
+    reset()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K, seed=19, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res["dual_huber_rof"] = {"alpha": alpha, "eps": eps, "p": p, "iters": K,
+                             "prox_calls": r["n_prox"], "ms": round(ms, 3),
+                             "iters_per_s": round(K / (ms * 1e-3), 1)}
+    log(f"Dual-Huber-ROF: {res['dual_huber_rof']}")
     return res
 
 

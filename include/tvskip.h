@@ -257,6 +257,39 @@ tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
                         const tvs_params* params, double* obj_trace,
                         uint8_t* theta_trace, tvs_report* report);
 
+/* ------------------------------------------------ light-prox problems
+ * ProxSkip on the dual of TV denoising, Sec. 2.1-2.2:
+ *
+ *   min_{|q_i| <= alpha}  F(q) = 1/2 |div q + b|^2 + eps / (2 alpha) |q|^2
+ *
+ * (eps = 0: Dual-ROF, eq. (6) up to its constant; eps > 0: Dual-Huber-ROF of
+ * Sec. 2.2, strongly convex with mu = eps / alpha).  grad F(q) = -D(div q +
+ * b) + mu q; the prox is the projection onto the alpha-ball (eq. (7), read as
+ * the projection onto radius alpha), so the prox step does not depend on
+ * gamma / p.  Step of Alg. "ProxSkip": w = q - step grad F(q), qhat = w + step
+ * h; if theta_k: q = P(w + (step - step / p) h), h += (p / step)(q - qhat);
+ * else q = qhat.  p = 1 is ProjGD (Sec. 2.1) bitwise.  The primal iterate is
+ * u = b + div q (tvs_div).  b: [H][W], q and h: [2][H][W], device, dtype,
+ * q and h in/out (start from zeros for a fresh run).  The coin is the stream
+ * of tvs_coin(seed, stream_id, k0 + k, p).  theta_trace (nullable, host,
+ * outer_iters bytes), n_prox_out (nullable, host).  Eight steps are fused
+ * per kernel launch; TVS_FLAG_GRAPH captures the run in one HIP graph. */
+typedef struct tvs_dual_rof_params {
+    double alpha;        /* radius of the dual ball (the TV weight), >= 0 */
+    double eps;          /* Huber smoothing, >= 0 */
+    double step;         /* gamma > 0, e.g. 1 / (8 + eps / alpha) */
+    double p;            /* projection probability in (0, 1] */
+    int64_t outer_iters;
+    uint64_t seed, stream_id;
+    int64_t k0;          /* first coin index */
+    int32_t flags;       /* TVS_FLAG_GRAPH */
+    int32_t reserved;
+} tvs_dual_rof_params;
+
+tvs_status tvs_dual_rof_proxskip(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* b,
+                                 void* q, void* h, const tvs_dual_rof_params* params,
+                                 uint8_t* theta_trace, int64_t* n_prox_out);
+
 /* ---------------------------------------------------------- batched form
  * Many independent ProxSkip TV-denoising problems (A = I, Sec. 2; the
  * batched workload of the build) of uneven sizes, solved together: each

@@ -13,7 +13,8 @@ from __future__ import annotations
 import ctypes as C
 
 from ._lib import (TVS_F32, TVS_F64, TVS_FLAG_GRAPH, TvsError, check, lib, tvs_batch_params,
-                   tvs_params, tvs_report, tvs_slice, tvs_solve_ext, tvs_state)
+                   tvs_dual_rof_params, tvs_params, tvs_report, tvs_slice, tvs_solve_ext,
+                   tvs_state)
 
 __all__ = [
     "TVS_F32", "TVS_F64", "TVS_FLAG_GRAPH", "TvsError",
@@ -22,6 +23,7 @@ __all__ = [
     "tvs_op_out_size", "tvs_op_apply", "tvs_op_adjoint", "tvs_op_norm",
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
+    "tvs_dual_rof_proxskip",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
     "tvs_proxskip_batched", "tvs_fgp_set_variant_batched", "tvs_fgp_autotune_batched",
     "tvs_fgp_query", "tvs_fgp_query_batched", "tvs_tune_clear", "tvs_tune_save", "tvs_tune_load",
@@ -310,6 +312,27 @@ def tvs_tune_save(ctx: int, path: str) -> None:
 
 def tvs_tune_load(ctx: int, path: str) -> None:
     check(lib().tvs_tune_load(C.c_void_p(ctx), str(path).encode()))
+
+
+# ------------------------------------------------------------ light prox (Sec. 2)
+def tvs_dual_rof_proxskip(ctx: int, b, q, h, alpha, eps, step, p, outer_iters, seed=0,
+                          stream_id=0, k0=0, graph=False, want_theta=False):
+    """ProxSkip on Dual-ROF (eps = 0) / Dual-Huber-ROF in place on q, h
+    ((2, H, W)).  Returns dict(n_prox, theta)."""
+    import numpy as np
+    H, W = b.shape
+    d = _dtype_code(b)
+    P = tvs_dual_rof_params(alpha=float(alpha), eps=float(eps), step=float(step), p=float(p),
+                            outer_iters=int(outer_iters), seed=int(seed),
+                            stream_id=int(stream_id), k0=int(k0),
+                            flags=TVS_FLAG_GRAPH if graph else 0, reserved=0)
+    th = np.zeros(max(int(outer_iters), 1), dtype=np.uint8) if want_theta else None
+    n = C.c_int64()
+    check(lib().tvs_dual_rof_proxskip(C.c_void_p(ctx), d, H, W, _ptr(b), _ptr(q, 2 * H * W, d),
+                                      _ptr(h, 2 * H * W, d), C.byref(P),
+                                      th.ctypes.data_as(C.POINTER(C.c_uint8)) if want_theta
+                                      else None, C.byref(n)))
+    return dict(n_prox=n.value, theta=th[:outer_iters] if want_theta else None)
 
 
 # ------------------------------------------------------------ batched form

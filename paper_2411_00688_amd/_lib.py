@@ -44,6 +44,13 @@ class tvs_slice(C.Structure):
                 ("p", C.c_double), ("seed", C.c_uint64), ("stream_id", C.c_uint64)]
 
 
+class tvs_dual_rof_params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("eps", C.c_double), ("step", C.c_double),
+                ("p", C.c_double), ("outer_iters", C.c_int64), ("seed", C.c_uint64),
+                ("stream_id", C.c_uint64), ("k0", C.c_int64), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class tvs_solve_ext(C.Structure):
     _fields_ = [("cnn", C.c_void_p), ("gap_tol", C.c_double), ("v_record", C.c_void_p),
                 ("max_record", C.c_int64), ("n_fallback", C.c_int64), ("n_recorded", C.c_int64)]
@@ -94,6 +101,9 @@ PROTOTYPES = {
     "tvs_pdhgskip_ex": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params),
                                   C.POINTER(tvs_solve_ext), dp, C.POINTER(C.c_uint8),
                                   C.POINTER(tvs_report)]),
+    "tvs_dual_rof_proxskip": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp,
+                                        C.POINTER(tvs_dual_rof_params), C.POINTER(C.c_uint8),
+                                        C.POINTER(C.c_int64)]),
     "tvs_fgp_variant_count": (C.c_int, []),
     "tvs_fgp_variant": (C.c_int, [C.c_int, ip, ip, ip]),
     "tvs_fgp_set_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int]),
