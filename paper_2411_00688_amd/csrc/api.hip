@@ -297,13 +297,9 @@ extern "C" tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
             e.half_spanf = (float)e.half_span;
             g.host[a] = e;
         }
-        // ray-driven backprojector: rays never share a pixel interval at one
-        // step (|Aq| >= 2^32) and a 60-pixel tile's rays fit the staged window
+        // the ray-driven float32 backprojector needs every angle to qualify
         g.rd_ok = true;
-        for (const JAngle& e : g.host) {
-            const double spread = 59.0 * std::fabs(e.B) * e.half_span + 2.0 + 64.0 + 4.0;
-            if (std::fabs(e.Aq) < 4294967296.0 || spread > 127.0) g.rd_ok = false;
-        }
+        for (const JAngle& e : g.host) g.rd_ok = g.rd_ok && joseph_rd_angle_ok(e);
         TVS_HIP(hipMalloc(&g.ang, n_ang * sizeof(JAngle)));
         TVS_HIP(hipMemcpy(g.ang, g.host.data(), n_ang * sizeof(JAngle), hipMemcpyHostToDevice));
         *out = op.release();

@@ -359,6 +359,16 @@ void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const 
 }
 
 // ------------------------------------------------------------------ Joseph
+// Byte offset 4 * (high word of V) of a float element.  The shift is written
+// as one instruction on the 32-bit high word; left to itself the compiler
+// forms it as a 64-bit funnel shift and a mask.
+__device__ __forceinline__ unsigned fx_byte_offset(long long V) {
+    const unsigned hw = (unsigned)((unsigned long long)V >> 32);
+    unsigned off;
+    __asm__("v_lshlrev_b32 %0, 2, %1" : "=v"(off) : "v"(hw));
+    return off;
+}
+
 template <typename T>
 struct JFwdArgs {
     const JAngle* ang;
@@ -369,6 +379,7 @@ struct JFwdArgs {
     T* y;
     int H, W, n_det;
     int epi;
+    int small;  // both padded copies span less than 4 GiB
     T tau;
 };
 
@@ -412,21 +423,62 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
         const T* row = img + (size_t)(lo > 0 ? lo : 0) * ld;
         if constexpr (sizeof(T) == 4) {
             // 32.32 fixed point: U = Aq d + Bq s + Cq exactly, floor(u) is the
-            // high word and the fraction the low word.
-            long long U = g.Aqi * (long long)d + g.Cqi + g.Bqi * (long long)lo;
+            // high word and the fraction the low word.  V adds the element
+            // offset of row s in the padded buffer (pads included) to the high
+            // word, so one 64-bit add per step advances both the sample and
+            // the row, and the high word indexes the left neighbour directly.
+            // (1 - f) v0 + f v1 is summed as v0 + f (v1 - v0), the two parts in
+            // separate accumulators, f (v1 - v0) scaled by 2^32.
+            const int s_lo = lo > 0 ? lo : 0;
+            long long V = g.Aqi * (long long)d + g.Cqi + g.Bqi * (long long)s_lo +
+                          (((long long)s_lo * ld + JPAD) << 32);
+            const long long dV = g.Bqi + ((long long)ld << 32);
+            const float* base = img - JPAD;
+            float acc0 = 0.0f, acc1 = 0.0f;
+            if (a.small) {
+                // byte offsets of the padded buffer fit 32 bits: the load takes
+                // the base in scalar registers and a 32-bit offset, formed
+                // from the high word by one shift.  Eight loads are issued
+                // before their sums.
+                int s = s_lo;
+                for (; s + 8 <= hi; s += 8) {
+                    float2 v[8];
+                    unsigned fr[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        __builtin_memcpy(&v[k], (const char*)base + fx_byte_offset(V), sizeof(float2));
+                        fr[k] = (unsigned)V;
+                        V += dV;
+                        // one induction variable: keeps the compiler from
+                        // splitting V into separate high- and low-word chains
+                        __asm__("" : "+v"(V));
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        acc0 += v[k].x;
+                        acc1 = fmaf((float)fr[k], v[k].y - v[k].x, acc1);
+                    }
+                }
+                for (; s < hi; ++s) {
+                    float2 v;
+                    __builtin_memcpy(&v, (const char*)base + fx_byte_offset(V), sizeof(v));
+                    acc0 += v.x;
+                    acc1 = fmaf((float)(unsigned)V, v.y - v.x, acc1);
+                    V += dV;
+                }
+            } else {
 #pragma unroll 8
-            for (int s = lo; s < hi; ++s) {
-                const int j0 = (int)(U >> 32);
-                const T f = (T)(unsigned)U * 2.3283064365386963e-10f;
-                // both neighbours in one 8-byte load (4-byte aligned, inside the
-                // padded row)
-                float2 v;
-                __builtin_memcpy(&v, row + j0, sizeof(v));
-                acc += (T(1) - f) * v.x;
-                acc += f * v.y;
-                U += g.Bqi;
-                row += ld;
+                for (int s = s_lo; s < hi; ++s) {
+                    // both neighbours in one 8-byte load (4-byte aligned, inside
+                    // the padded row)
+                    float2 v;
+                    __builtin_memcpy(&v, base + (size_t)(unsigned)(V >> 32), sizeof(v));
+                    acc0 += v.x;
+                    acc1 = fmaf((float)(unsigned)V, v.y - v.x, acc1);
+                    V += dV;
+                }
             }
+            acc = acc0 + acc1 * 2.3283064365386963e-10f;
         } else {
 #pragma unroll 4
             for (int s = lo; s < hi; ++s) {
@@ -475,6 +527,8 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.n_det = op->joseph.n_det;
     a.epi = epi;
     a.tau = tau;
+    a.small = (size_t)op->H * a.x_ld * sizeof(T) < (1ull << 32) &&
+              (size_t)op->W * a.xT_ld * sizeof(T) < (1ull << 32);
     dim3 grid(div_up(a.n_det, 64), op->joseph.n_ang);
     hipLaunchKernelGGL((joseph_fwd_kernel<T, 4>), grid, dim3(256), 0, ctx->stream, a);
     TVS_LAUNCH_CHECK();
@@ -696,23 +750,39 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // Ray-driven backprojector for float32 data and detector spacing >= pixel
-// (|A| >= 1, so two rays never sample the same pixel interval at one step).
+// (|Aq| >= 2^32: at one step two rays never floor to the same pixel).
 //
-// Block: a 60 x 60 pixel tile and one group of angles (angles g, g + G, ...);
-// 4 wavefronts, each owning 15 rows (row-stepping angles) and 15 columns
-// (column-stepping angles) of the tile.  For one angle and one row s, the 64
-// lanes take 64 consecutive rays, compute each ray's sample at that row with
-// the projector's exact fixed-point arithmetic, and scatter its two weights
-// into a per-wavefront LDS line of the 60 pixels (distinct rays land on
-// distinct pixels, so no atomics); each pixel lane then reads its total.  The
-// sinogram window of every angle of the group is staged into LDS once per
-// block.  Each block writes its group's partial image; joseph_adj_sum adds the
-// G partials in a fixed order and applies the epilogue, so the result is
-// deterministic.
-static constexpr int RD_P = 60;     // tile side
-static constexpr int RD_L = 15;     // rows / columns per wavefront
+// Block: a 52 x 52 pixel tile and one group of angles (g, g + G, ...), four
+// wavefronts.  For a row-stepping angle wavefront w owns tile rows
+// 13 w .. 13 w + 12, for a column-stepping angle the same columns.  Per
+// (wavefront, angle) the 64 lanes take 64 consecutive rays that include every
+// ray reaching the wavefront's strip; a lane keeps its ray, its sinogram value
+// and its exact 32.32 position (one 64-bit add per step) for all 13 steps.
+// Per step the ray lanes scatter their two weights into a per-wavefront LDS
+// line of the strip's 52 pixels (distinct rays land on distinct slots, so no
+// atomics and no bank conflicts) and the pixel lanes read their totals into
+// registers.  Row-stepping sums are held per (row, lane = column),
+// column-stepping ones per (column, lane = row) and meet through an LDS
+// transpose, so every pixel's sum has one fixed order.  Each block writes its
+// group's partial image; joseph_adj_sum adds the G partials in order and
+// applies the epilogue, so the result is deterministic.
+static constexpr int RD_P = 52;     // tile side
+static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 16;  // angles per group
+static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
+static constexpr int RD_LINE = 132; // floats per wavefront line: 2 x 64 slots + read slack
+static_assert(RD_P + 2 <= 64, "a line's slots fit one float2 per lane");
+
+// The ray-driven path applies to an angle when rays are at least a pixel
+// apart along the interpolation axis, the rays of a tile fit the staged
+// window (span + the margins of rd_window) and the rays of a wavefront's
+// strip fit 64 lanes (span + the margins of rd_entry).
+bool joseph_rd_angle_ok(const JAngle& e) {
+    if (std::fabs(e.Aq) < 4294967296.0) return false;
+    const double t = (RD_P + 1) * e.half_span, b = std::fabs(e.B) * e.half_span;
+    return t + (RD_P - 1) * b + 6.0 <= RD_NB && t + (RD_L - 1) * b + 4.0 <= 64.0;
+}
 
 template <typename T>
 struct JAdjRdArgs {
@@ -723,14 +793,32 @@ struct JAdjRdArgs {
     T* part;  // [groups][H][W]
 };
 
-// first bin of the staged window of angle g for the tile at (i0, j0)
+// real-valued index of the ray whose sample is at u = v at step s
+__device__ __forceinline__ double rd_ray_at(const JAngle& g, double v, double s) {
+    return (v - fma(g.B, s, g.C)) * g.inv_A;
+}
+
+// First staged bin of angle g for the tile: three rays before every ray whose
+// sample reaches u in [t0 - 1, t0 + RD_P) at one of the tile's steps.
 __device__ __forceinline__ int rd_window(const JAngle& g, int i0, int j0) {
     const int s0 = g.cls ? j0 : i0, t0 = g.cls ? i0 : j0;
-    const double Ka = fma(g.B, (double)s0, g.C), Kb = fma(g.B, (double)(s0 + RD_P - 1), g.C);
     const double lo = (double)(t0 - 1), hi = (double)(t0 + RD_P);
-    const double e1 = (lo - Ka) * g.inv_A, e2 = (hi - Ka) * g.inv_A;
-    const double e3 = (lo - Kb) * g.inv_A, e4 = (hi - Kb) * g.inv_A;
+    const double e1 = rd_ray_at(g, lo, s0), e2 = rd_ray_at(g, hi, s0);
+    const double e3 = rd_ray_at(g, lo, s0 + RD_P - 1), e4 = rd_ray_at(g, hi, s0 + RD_P - 1);
     return (int)floor(fmin(fmin(e1, e2), fmin(e3, e4))) - 3;
+}
+
+// Lane window of wavefront w for angle g: its first ray d0 (one before every
+// ray that reaches the strip) and the 32.32 position of ray d0 at the strip's
+// first step, relative to pixel t0 - 1 of the interpolation axis.
+__device__ __forceinline__ void rd_entry(const JAngle& g, int i0, int j0, int w, int& d0,
+                                         long long& K) {
+    const int s_first = (g.cls ? j0 : i0) + RD_L * w, t0 = g.cls ? i0 : j0;
+    const double lo = (double)(t0 - 1), hi = (double)(t0 + RD_P);
+    const double e1 = rd_ray_at(g, lo, s_first), e2 = rd_ray_at(g, hi, s_first);
+    const double e3 = rd_ray_at(g, lo, s_first + RD_L - 1), e4 = rd_ray_at(g, hi, s_first + RD_L - 1);
+    d0 = (int)floor(fmin(fmin(e1, e2), fmin(e3, e4))) - 1;
+    K = g.Aqi * (long long)d0 + g.Bqi * (long long)s_first + g.Cqi - ((long long)(t0 - 1) << 32);
 }
 
 // A value every lane of the wavefront holds, moved to scalar registers.
@@ -740,89 +828,71 @@ __device__ __forceinline__ long long wave_uniform64(long long v) {
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-// Index of the ray whose sample reaches the near edge of the tile's pixel
-// range at step s (the smaller of the two edges' ray indices, real-valued).
-// The 64-ray window of a step starts one ray before it; within +-1 of that
-// start the window still covers every ray that touches the tile (rays are at
-// least one pixel apart, a tile row needs at most 62 of them), so rounding
-// in this value does not matter.
-__device__ __forceinline__ double rd_edge_ray(const JAngle& gg, int s, int t0) {
-    const double Kr = fma(gg.B, (double)s, gg.C);
-    return fmin(((double)(t0 - 1) - Kr) * gg.inv_A, ((double)(t0 + RD_P) - Kr) * gg.inv_A);
+// The steps of one angle for one wavefront.  U: the lane's ray position
+// relative to pixel t0 - 1 (high word h = pixel index + 1 in the strip,
+// valid in [0, RD_P]); val: the ray's weighted sinogram value.  The line is
+// two arrays of 64 slots (plus slack for the reads of lanes >= RD_P): lx[h] takes (1 - f) val (pixel h - 1), ly[h + 1]
+// takes f val (pixel h), so pixel c reads lx[c + 1] + ly[c + 1].  The
+// compiler barriers keep the clear, scatter and gather phases in order across
+// lanes (lanes exchange data through the line, which per-lane alias analysis
+// does not see).
+template <bool FULL>
+__device__ __forceinline__ void rd_angle(float* ln, int lane, int n_s, long long U, long long dU,
+                                         float val, float (&acc)[RD_L]) {
+#pragma unroll
+    for (int k = 0; k < RD_L; ++k) {
+        if (FULL || k < n_s) {
+            reinterpret_cast<float2*>(ln)[lane] = make_float2(0.0f, 0.0f);
+            __asm__ __volatile__("" ::: "memory");
+            if ((unsigned long long)U < ((unsigned long long)(RD_P + 1) << 32)) {
+                // the projector's weights, rounded as the projector rounds
+                // them, so the two operators are transposes bit for bit
+                const int h = (int)(U >> 32);
+                const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
+                ln[h] = (1.0f - f) * val;
+                ln[64 + h + 1] = f * val;
+            }
+            __asm__ __volatile__("" ::: "memory");
+            // every lane reads (lanes >= RD_P read slots no pixel uses): no
+            // divergent update of the accumulator array
+            acc[k] += ln[lane + 1] + ln[64 + lane + 1];
+            __asm__ __volatile__("" ::: "memory");
+            U += dU;
+        }
+    }
 }
 
-// One angle for the wavefront's RD_L steps s_first .. s_first + RD_L - 1 and
-// the tile's pixels t0 .. t0 + RD_P - 1 along the interpolation axis.  The
-// window start d0 and its exact 32.32 position Aq d0 + Bq s + Cq are
-// wave-uniform and advance by integer additions per step (scalar unit); lane
-// l takes ray d0 + l at position + l Aq, the same integer the projector forms,
-// so the scatter is the exact transpose of the projector.  Each LDS line is
-// two float arrays of 64 slots (slot 2 + p is pixel p; slots 0, 1 and 62, 63
-// absorb samples outside the tile, clamped there, so every lane writes
-// unconditionally): lx collects (1 - f) y of the ray whose sample floors to
-// the pixel, ly collects f y of the ray that floors to the pixel before.
-// Distinct rays land on distinct slots, so both scatters are free of bank
-// conflicts.  RD_B steps go through RD_B lines at once, so the LDS round
-// trips of a batch overlap; the compiler barriers keep the clear, scatter and
-// gather phases in order across lanes (the lanes of a wavefront exchange
-// data through the line, which per-lane alias analysis does not see).
-static constexpr int RD_B = 1;  // steps per batch (5 measured slower: more LDS per wave, lower occupancy)
-static_assert(RD_L % RD_B == 0, "batches must tile the wavefront's steps");
-
-__device__ __forceinline__ void rd_angle(const JAngle& gg, const float* ys, int ws, int s_first,
-                                         int t0, int n_step, int lane, float* ln,
-                                         float (&acc)[RD_L]) {
-    const float wgt = (float)gg.wgt;
-    const long long AqL = gg.Aqi * (long long)lane;
-    // window start in 32.32 fixed point: E(s) = E0 + (s - s_first) dE
-    const double e0 = rd_edge_ray(gg, s_first, t0);
-    const double de = -gg.B * gg.inv_A;
-    long long E = wave_uniform64((long long)llrint(ldexp(e0, 32)));
-    const long long dE = wave_uniform64((long long)llrint(ldexp(de, 32)));
-    long long K = wave_uniform64(gg.Bqi * (long long)s_first + gg.Cqi);
-#pragma unroll
-    for (int b0 = 0; b0 < RD_L; b0 += RD_B) {
-        float val[RD_B], f[RD_B];
-        int lt[RD_B];
-#pragma unroll
-        for (int k = 0; k < RD_B; ++k) {
-            const int d0 = (int)(E >> 32) - 1;
-            int bi = d0 - ws + lane;
-            bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
-            val[k] = wgt * ys[bi];
-            const long long U = gg.Aqi * (long long)d0 + K + AqL;
-            f[k] = (float)(unsigned)U * 2.3283064365386963e-10f;
-            const int l = (int)(U >> 32) - t0;
-            lt[k] = l < -2 ? -2 : (l > RD_P ? RD_P : l);
-            E += dE;
-            K += gg.Bqi;
-        }
-#pragma unroll
-        for (int k = 0; k < RD_B; ++k)
-            reinterpret_cast<float2*>(ln + 128 * k)[lane] = make_float2(0.0f, 0.0f);
-        __asm__ __volatile__("" ::: "memory");
-#pragma unroll
-        for (int k = 0; k < RD_B; ++k) {
-            if (s_first + b0 + k < n_step) {
-                ln[128 * k + lt[k] + 2] = (1.0f - f[k]) * val[k];
-                ln[128 * k + 64 + lt[k] + 3] = f[k] * val[k];
-            }
-        }
-        __asm__ __volatile__("" ::: "memory");
-        if (lane < RD_P) {
-#pragma unroll
-            for (int k = 0; k < RD_B; ++k)
-                if (s_first + b0 + k < n_step)
-                    acc[b0 + k] += ln[128 * k + lane + 2] + ln[128 * k + 64 + lane + 2];
-        }
-        __asm__ __volatile__("" ::: "memory");
+// All angles of one class of the block's group for wavefront w.
+template <int CLS>
+__device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float (*yS)[RD_NB],
+                                         const int* wst, const int* ecls, const int (*eD)[4],
+                                         const long long (*eK)[4], float* ln, int g, int G,
+                                         int na_g, int w, int lane, int n_s, float (&acc)[RD_L]) {
+    if (n_s <= 0) return;
+    for (int m = 0; m < na_g; ++m) {
+        if (ecls[m] != CLS) continue;
+        const JAngle& gg = a.ang[g + m * G];
+        const int d0 = __builtin_amdgcn_readfirstlane(eD[m][w]);
+        const int ws = __builtin_amdgcn_readfirstlane(wst[m]);
+        const long long K = wave_uniform64(eK[m][w]);
+        int bi = d0 - ws + lane;
+        bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
+        const float val = yS[m][bi];
+        const long long U = K + gg.Aqi * (long long)lane;
+        if (n_s >= RD_L)
+            rd_angle<true>(ln, lane, n_s, U, gg.Bqi, val, acc);
+        else
+            rd_angle<false>(ln, lane, n_s, U, gg.Bqi, val, acc);
     }
 }
 
 __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
     __shared__ float yS[RD_MAXA][RD_NB];
     __shared__ int wst[RD_MAXA];
-    __shared__ __attribute__((aligned(16))) float line[4][RD_B * 128];
+    __shared__ int ecls[RD_MAXA];
+    __shared__ int eD[RD_MAXA][4];
+    __shared__ long long eK[RD_MAXA][4];
+    __shared__ __attribute__((aligned(16))) float line[4][RD_LINE];
     __shared__ float tileT[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
@@ -833,37 +903,43 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int na_g = (a.n_ang - g + G - 1) / G;
-    for (int m = tid; m < na_g; m += 256) wst[m] = rd_window(a.ang[g + m * G], i0, j0);
+    if (tid < na_g) {
+        const JAngle& gg = a.ang[g + tid * G];
+        wst[tid] = rd_window(gg, i0, j0);
+        ecls[tid] = gg.cls;
+    }
+    if (tid < 4 * na_g) {
+        const int m = tid >> 2, ww = tid & 3;
+        rd_entry(a.ang[g + m * G], i0, j0, ww, eD[m][ww], eK[m][ww]);
+    }
     __syncthreads();
     for (int idx = tid; idx < na_g * RD_NB; idx += 256) {
         const int m = idx / RD_NB, bb = idx - m * RD_NB;
         const int d = wst[m] + bb;
-        yS[m][bb] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
+        const JAngle& gg = a.ang[g + m * G];
+        yS[m][bb] = (d >= 0 && d < a.n_det) ? (float)gg.wgt * a.y[(size_t)(g + m * G) * a.n_det + d]
+                                            : 0.0f;
     }
     __syncthreads();
     float accR[RD_L], accC[RD_L];
 #pragma unroll
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
-    for (int m = 0; m < na_g; ++m) {
-        const JAngle gg = a.ang[g + m * G];
-        const int ws = __builtin_amdgcn_readfirstlane(wst[m]);
-        if (gg.cls == 0)
-            rd_angle(gg, yS[m], ws, i0 + RD_L * w, j0, a.H, lane, line[w], accR);
-        else
-            rd_angle(gg, yS[m], ws, j0 + RD_L * w, i0, a.W, lane, line[w], accC);
-    }
-    // column-stepping sums are held per (row = lane, column = 15 w + c): transpose
+    const int nR = __builtin_amdgcn_readfirstlane(a.H - (i0 + RD_L * w));
+    const int nC = __builtin_amdgcn_readfirstlane(a.W - (j0 + RD_L * w));
+    rd_class<0>(a, yS, wst, ecls, eD, eK, line[w], g, G, na_g, w, lane, nR, accR);
+    rd_class<1>(a, yS, wst, ecls, eD, eK, line[w], g, G, na_g, w, lane, nC, accC);
+    // column-stepping sums are held per (column = 13 w + k, row = lane): transpose
     if (lane < RD_P) {
 #pragma unroll
-        for (int c = 0; c < RD_L; ++c) tileT[lane][RD_L * w + c] = accC[c];
+        for (int k = 0; k < RD_L; ++k) tileT[lane][RD_L * w + k] = accC[k];
     }
     __syncthreads();
     const size_t plane = (size_t)a.H * a.W;
 #pragma unroll
-    for (int r = 0; r < RD_L; ++r) {
-        const int i = i0 + RD_L * w + r, j = j0 + lane;
+    for (int k = 0; k < RD_L; ++k) {
+        const int i = i0 + RD_L * w + k, j = j0 + lane;
         if (lane < RD_P && i < a.H && j < a.W)
-            a.part[(size_t)g * plane + (size_t)i * a.W + j] = accR[r] + tileT[RD_L * w + r][lane];
+            a.part[(size_t)g * plane + (size_t)i * a.W + j] = accR[k] + tileT[RD_L * w + k][lane];
     }
 }
 

@@ -131,8 +131,8 @@ struct JosephGeom {
     double pixel = 0, det_spacing = 0;
     JAngle* ang = nullptr;   // device table
     std::vector<JAngle> host;
-    // the ray-driven float32 backprojector applies (|A| >= 1 and the staged
-    // sinogram window of a 60-pixel tile fits 128 bins for every angle)
+    // the ray-driven float32 backprojector applies (joseph_rd_angle_ok for
+    // every angle)
     bool rd_ok = false;
 };
 
@@ -267,6 +267,7 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
 template <typename T>
 void launch_pad_copy(tvs_ctx* ctx, int H, int W, const T* x, T* xp, T* xTp);
 int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op);
+bool joseph_rd_angle_ok(const JAngle& e);
 template <typename T>
 void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
                        const PrimalStep<T>* ps);
