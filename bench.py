@@ -374,14 +374,15 @@ def fgp_hbm(T, ctx, n, Kin):
     return res
 
 
-def light_prox_bench(T, ctx, chunk=500, max_iters=50000, tol=1e-5):
+def light_prox_bench(T, ctx):
     """ProxSkip on the light-prox problems (Sec. 2.1-2.2) on a 200 x 300
-    shapes-like phantom with noise 0.05, float64.  Dual-ROF (alpha 0.5, step
-    1/8): for p in {1 (ProjGD), 0.5, 0.3, 0.1, 0.01}, the first chunk of
-    `chunk` iterations after which the TV-prox relative duality gap of q is
-    <= tol (a certificate: no reference solution needed), then the time of an
-    un-instrumented run of that many iterations.  Dual-Huber-ROF (alpha 0.55,
-    eps 0.01, p 0.04767, 5000 iterations): throughput and projections."""
+    shapes-like phantom with noise 0.05, float64, the paper's protocol:
+    Dual-ROF (alpha 0.5, step 1/8), p in {1 (ProjGD), 0.5, 0.3, 0.1, 0.01},
+    50000 iterations each, the l2 error of u_K = b + div q_K against u*
+    (ProjGD, 200000 iterations); Dual-Huber-ROF (alpha 0.55, eps 0.01, step
+    1/(8 + eps/alpha), p 0.04767), 5000 iterations, the iteration at which the
+    relative error first drops below 1e-6 (u* from 50000 ProjGD iterations)
+    and the mean projection count over 30 coin streams."""
     import numpy as np
     import torch
     import synth
@@ -391,53 +392,75 @@ def light_prox_bench(T, ctx, chunk=500, max_iters=50000, tol=1e-5):
     b = torch.tensor(u + 0.05 * eta, dtype=torch.float64, device=dev)
     q = torch.zeros(2, H, W, dtype=torch.float64, device=dev)
     hh = torch.zeros_like(q)
-    res = {"image": [H, W], "dtype": "f64", "gap_tol": tol, "dual_rof": {}}
+    dq = torch.empty(H, W, dtype=torch.float64, device=dev)
 
     def reset():
         q.zero_()
         hh.zero_()
 
+    def primal():
+        T.tvs_div(ctx, q, dq)
+        return b + dq
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    res = {"image": [H, W], "dtype": "f64"}
+    # Dual-ROF
+    reset()
+    T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, 1.0, 200000, graph=True)
+    u_star = primal().clone()
+    nrm = torch.linalg.norm(u_star).item()
+    rof = {}
     for p in (1.0, 0.5, 0.3, 0.1, 0.01):
+        K = 50000
         reset()
-        k_hit, nprox = None, 0
-        for k0 in range(0, max_iters, chunk):
-            r = T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, chunk, seed=17, k0=k0)
-            nprox += r["n_prox"]
-            gap, primal = T.tvs_tv_gap(ctx, b, 0.5, 0, q)
-            if gap / primal <= tol:
-                k_hit = k0 + chunk
-                break
-        entry = {"iters": k_hit, "prox_calls": nprox if k_hit else None}
-        if k_hit:
-            reset()
-            T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, k_hit, seed=17, graph=True)
-            reset()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, k_hit, seed=17, graph=True)
-            e1.record()
-            torch.cuda.synchronize()
-            entry["ms"] = round(e0.elapsed_time(e1), 3)
-            entry["us_per_iter"] = round(1e3 * e0.elapsed_time(e1) / k_hit, 3)
-        res["dual_rof"][f"p={p}"] = entry
-        log(f"Dual-ROF p={p}: {entry}")
-    # Dual-Huber-ROF at the paper's p (Sec. 2.2)
+        T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, K, seed=17, graph=True)
+        reset()
+        r, ms = timed(lambda: T.tvs_dual_rof_proxskip(ctx, b, q, hh, 0.5, 0.0, 0.125, p, K,
+                                                      seed=17, graph=True))
+        err = torch.linalg.norm(primal() - u_star).item() / nrm
+        rof[f"p={p}"] = {"iters": K, "prox_calls": r["n_prox"], "ms": round(ms, 3),
+                         "us_per_iter": round(1e3 * ms / K, 4), "rel_l2_err": err}
+        log(f"Dual-ROF p={p}: {rof[f'p={p}']}")
+    res["dual_rof"] = {"alpha": 0.5, "step": 0.125, "u_star": "ProjGD, 200000 iterations",
+                       "runs": rof}
+    # Dual-Huber-ROF
     alpha, eps, p, K = 0.55, 0.01, 0.04767, 5000
     step = 1.0 / (8.0 + eps / alpha)
     reset()
+    T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, 1.0, 50000, graph=True)
+    u_star = primal().clone()
+    nrm = torch.linalg.norm(u_star).item()
+    reset()
+    hit = None
+    for k0 in range(0, K, 50):
+        T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, 50, seed=19, k0=k0)
+        if hit is None and torch.linalg.norm(primal() - u_star).item() / nrm < 1e-6:
+            hit = k0 + 50
+    reset()
     T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K, seed=19, graph=True)
     reset()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    r = T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K, seed=19, graph=True)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    res["dual_huber_rof"] = {"alpha": alpha, "eps": eps, "p": p, "iters": K,
-                             "prox_calls": r["n_prox"], "ms": round(ms, 3),
-                             "iters_per_s": round(K / (ms * 1e-3), 1)}
+    r, ms = timed(lambda: T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K,
+                                                  seed=19, graph=True))
+    err = torch.linalg.norm(primal() - u_star).item() / nrm
+    counts = []
+    for sd in range(30):
+        reset()
+        counts.append(T.tvs_dual_rof_proxskip(ctx, b, q, hh, alpha, eps, step, p, K,
+                                              seed=1000 + sd)["n_prox"])
+    res["dual_huber_rof"] = {"alpha": alpha, "eps": eps, "step": step, "p": p, "iters": K,
+                             "prox_calls": r["n_prox"], "mean_prox_calls_30_streams":
+                             float(np.mean(counts)), "ms": round(ms, 3),
+                             "iters_per_s": round(K / (ms * 1e-3), 1), "rel_l2_err": err,
+                             "iters_to_1e-6": hit,
+                             "ms_to_1e-6": round(ms * hit / K, 3) if hit else None}
     log(f"Dual-Huber-ROF: {res['dual_huber_rof']}")
     return res
 

@@ -161,7 +161,8 @@ tvs_status tvs_fgp_variant(int index, int* tile_w, int* tile_h, int* steps);
  * default. */
 tvs_status tvs_fgp_set_variant(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, int index);
 /* Times every variant on a seeded random H x W image (inner_iters FGP
- * iterations, `reps` repetitions, HIP events), keeps the fastest and returns
+ * iterations, `reps` repetitions, HIP events; three rounds over all variants,
+ * each variant's best round counted), keeps the fastest and returns
  * it in *best_index (nullable); ms_per_iter_out (nullable, host, variant
  * count doubles) gets each variant's milliseconds per FGP iteration (-1 if
  * not available for the dtype).  Synchronises; allocates temporary device
