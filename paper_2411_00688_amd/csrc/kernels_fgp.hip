@@ -245,6 +245,8 @@ struct FgpVariant {
 static const FgpVariant kFgpVariants[] = {
     {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8},
     {64, 16, 1}, {64, 16, 4}, {64, 32, 4}, {16, 16, 4}, {64, 32, 8},
+    // small images (latency-bound: fewer launches per prox call)
+    {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2},
 };
 
 template <typename T>
@@ -258,6 +260,7 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     }
     TVS_FGPV(32, 32, 1) TVS_FGPV(32, 32, 2) TVS_FGPV(32, 32, 4) TVS_FGPV(32, 32, 8)
     TVS_FGPV(64, 16, 1) TVS_FGPV(64, 16, 4) TVS_FGPV(64, 32, 4) TVS_FGPV(16, 16, 4)
+    TVS_FGPV(16, 16, 8) TVS_FGPV(32, 16, 4) TVS_FGPV(32, 16, 8) TVS_FGPV(16, 16, 2)
     if (sizeof(T) == 4) { TVS_FGPV(64, 32, 8) }
 #undef TVS_FGPV
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
@@ -350,6 +353,7 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
     }
     TVS_FGPB(32, 32, 1) TVS_FGPB(32, 32, 2) TVS_FGPB(32, 32, 4) TVS_FGPB(32, 32, 8)
     TVS_FGPB(64, 16, 1) TVS_FGPB(64, 16, 4) TVS_FGPB(64, 32, 4) TVS_FGPB(16, 16, 4)
+    TVS_FGPB(16, 16, 8) TVS_FGPB(32, 16, 4) TVS_FGPB(32, 16, 8) TVS_FGPB(16, 16, 2)
     if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
 #undef TVS_FGPB
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
