@@ -771,8 +771,7 @@ static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 16;  // angles per group
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
-static constexpr int RD_LINE = 132; // floats per wavefront line: 2 x 64 slots + read slack
-static_assert(RD_P + 2 <= 64, "a line's slots fit one float2 per lane");
+static_assert(RD_P + 1 < 63, "pixel lanes (and lane RD_P, past the tile) stay clear of the discard lane 63");
 
 // The ray-driven path applies to an angle when rays are at least a pixel
 // apart along the interpolation axis, the rays of a tile fit the staged
@@ -828,35 +827,40 @@ __device__ __forceinline__ long long wave_uniform64(long long v) {
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
+// Permute byte addresses of one step: (1 - f) val goes to pixel lane h - 1,
+// f val to pixel lane h, with h the high word of U; rays outside the strip
+// push to lane 63, which is no pixel (h - 1 = -1 wraps there too).
+__device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
+    const bool in = (unsigned long long)U < ((unsigned long long)(RD_P + 1) << 32);
+    const unsigned hw = (unsigned)((unsigned long long)U >> 32);
+    int h4;
+    // 4 h as one shift of the high word (the compiler would form it as a
+    // 64-bit funnel shift and a mask)
+    __asm__("v_lshlrev_b32 %0, 2, %1" : "=v"(h4) : "v"(hw));
+    da = in ? h4 - 4 : 4 * 63;
+    db = in ? h4 : 4 * 63;
+}
+
 // The steps of one angle for one wavefront.  U: the lane's ray position
-// relative to pixel t0 - 1 (high word h = pixel index + 1 in the strip,
-// valid in [0, RD_P]); val: the ray's weighted sinogram value.  The line is
-// two arrays of 64 slots (plus slack for the reads of lanes >= RD_P): lx[h] takes (1 - f) val (pixel h - 1), ly[h + 1]
-// takes f val (pixel h), so pixel c reads lx[c + 1] + ly[c + 1].  The
-// compiler barriers keep the clear, scatter and gather phases in order across
-// lanes (lanes exchange data through the line, which per-lane alias analysis
-// does not see).
+// relative to pixel t0 - 1 (high word h = pixel index + 1 in the strip, valid
+// in [0, RD_P]); val: the ray's weighted sinogram value.  Each step moves the
+// ray lanes' two weights to the pixel lanes with forward permutes (lanes no
+// ray pushes to receive 0; distinct rays never share a destination) and adds
+// them to that step's accumulator.
 template <bool FULL>
-__device__ __forceinline__ void rd_angle(float* ln, int lane, int n_s, long long U, long long dU,
-                                         float val, float (&acc)[RD_L]) {
+__device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long long dU, float val,
+                                         float (&acc)[RD_L]) {
 #pragma unroll
     for (int k = 0; k < RD_L; ++k) {
         if (FULL || k < n_s) {
-            reinterpret_cast<float2*>(ln)[lane] = make_float2(0.0f, 0.0f);
-            __asm__ __volatile__("" ::: "memory");
-            if ((unsigned long long)U < ((unsigned long long)(RD_P + 1) << 32)) {
-                // the projector's weights, rounded as the projector rounds
-                // them, so the two operators are transposes bit for bit
-                const int h = (int)(U >> 32);
-                const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
-                ln[h] = (1.0f - f) * val;
-                ln[64 + h + 1] = f * val;
-            }
-            __asm__ __volatile__("" ::: "memory");
-            // every lane reads (lanes >= RD_P read slots no pixel uses): no
-            // divergent update of the accumulator array
-            acc[k] += ln[lane + 1] + ln[64 + lane + 1];
-            __asm__ __volatile__("" ::: "memory");
+            // the projector's weights, rounded as the projector rounds them,
+            // so the two operators are transposes bit for bit
+            const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
+            int da, db;
+            rd_dest(U, da, db);
+            const float ra = __int_as_float(__builtin_amdgcn_ds_permute(da, __float_as_int((1.0f - f) * val)));
+            const float rb = __int_as_float(__builtin_amdgcn_ds_permute(db, __float_as_int(f * val)));
+            acc[k] += ra + rb;
             U += dU;
         }
     }
@@ -866,7 +870,7 @@ __device__ __forceinline__ void rd_angle(float* ln, int lane, int n_s, long long
 template <int CLS>
 __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float (*yS)[RD_NB],
                                          const int* wst, const int* ecls, const int (*eD)[4],
-                                         const long long (*eK)[4], float* ln, int g, int G,
+                                         const long long (*eK)[4], int g, int G,
                                          int na_g, int w, int lane, int n_s, float (&acc)[RD_L]) {
     if (n_s <= 0) return;
     for (int m = 0; m < na_g; ++m) {
@@ -880,9 +884,9 @@ __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float
         const float val = yS[m][bi];
         const long long U = K + gg.Aqi * (long long)lane;
         if (n_s >= RD_L)
-            rd_angle<true>(ln, lane, n_s, U, gg.Bqi, val, acc);
+            rd_angle<true>(lane, n_s, U, gg.Bqi, val, acc);
         else
-            rd_angle<false>(ln, lane, n_s, U, gg.Bqi, val, acc);
+            rd_angle<false>(lane, n_s, U, gg.Bqi, val, acc);
     }
 }
 
@@ -892,7 +896,6 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     __shared__ int ecls[RD_MAXA];
     __shared__ int eD[RD_MAXA][4];
     __shared__ long long eK[RD_MAXA][4];
-    __shared__ __attribute__((aligned(16))) float line[4][RD_LINE];
     __shared__ float tileT[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
@@ -926,8 +929,8 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
     const int nR = __builtin_amdgcn_readfirstlane(a.H - (i0 + RD_L * w));
     const int nC = __builtin_amdgcn_readfirstlane(a.W - (j0 + RD_L * w));
-    rd_class<0>(a, yS, wst, ecls, eD, eK, line[w], g, G, na_g, w, lane, nR, accR);
-    rd_class<1>(a, yS, wst, ecls, eD, eK, line[w], g, G, na_g, w, lane, nC, accC);
+    rd_class<0>(a, yS, wst, ecls, eD, eK, g, G, na_g, w, lane, nR, accR);
+    rd_class<1>(a, yS, wst, ecls, eD, eK, g, G, na_g, w, lane, nC, accC);
     // column-stepping sums are held per (column = 13 w + k, row = lane): transpose
     if (lane < RD_P) {
 #pragma unroll
