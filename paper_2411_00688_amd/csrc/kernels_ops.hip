@@ -771,7 +771,7 @@ static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 16;  // angles per group
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
-static_assert(RD_P + 1 < 63, "pixel lanes (and lane RD_P, past the tile) stay clear of the discard lane 63");
+static_assert(RD_P + 1 < 62, "pixel lanes (and lane RD_P, past the tile) stay clear of the discard lanes 62, 63");
 
 // The ray-driven path applies to an angle when rays are at least a pixel
 // apart along the interpolation axis, the rays of a tile fit the staged
@@ -829,7 +829,8 @@ __device__ __forceinline__ long long wave_uniform64(long long v) {
 
 // Permute byte addresses of one step: (1 - f) val goes to pixel lane h - 1,
 // f val to pixel lane h, with h the high word of U; rays outside the strip
-// push to lane 63, which is no pixel (h - 1 = -1 wraps there too).
+// push to lanes 62 and 63, which are no pixels (h - 1 = -1 wraps to 63 too;
+// the permute takes the lane modulo 64).
 __device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
     const bool in = (unsigned long long)U < ((unsigned long long)(RD_P + 1) << 32);
     const unsigned hw = (unsigned)((unsigned long long)U >> 32);
@@ -837,8 +838,8 @@ __device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
     // 4 h as one shift of the high word (the compiler would form it as a
     // 64-bit funnel shift and a mask)
     __asm__("v_lshlrev_b32 %0, 2, %1" : "=v"(h4) : "v"(hw));
-    da = in ? h4 - 4 : 4 * 63;
     db = in ? h4 : 4 * 63;
+    da = db - 4;
 }
 
 // The steps of one angle for one wavefront.  U: the lane's ray position
@@ -850,16 +851,20 @@ __device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
 template <bool FULL>
 __device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long long dU, float val,
                                          float (&acc)[RD_L]) {
+    const float vs = val * 2.3283064365386963e-10f;  // val 2^-32, exact
 #pragma unroll
     for (int k = 0; k < RD_L; ++k) {
         if (FULL || k < n_s) {
             // the projector's weights, rounded as the projector rounds them,
             // so the two operators are transposes bit for bit
-            const float f = (float)(unsigned)U * 2.3283064365386963e-10f;
+            // (1 - f = fl(1 - fr 2^-32), f val = fl(fr (val 2^-32)), fr the
+            // float fraction word: the same roundings in fewer operations)
+            const float fr = (float)(unsigned)U;
             int da, db;
             rd_dest(U, da, db);
-            const float ra = __int_as_float(__builtin_amdgcn_ds_permute(da, __float_as_int((1.0f - f) * val)));
-            const float rb = __int_as_float(__builtin_amdgcn_ds_permute(db, __float_as_int(f * val)));
+            const float wa = fmaf(fr, -2.3283064365386963e-10f, 1.0f) * val, wb = fr * vs;
+            const float ra = __int_as_float(__builtin_amdgcn_ds_permute(da, __float_as_int(wa)));
+            const float rb = __int_as_float(__builtin_amdgcn_ds_permute(db, __float_as_int(wb)));
             acc[k] += ra + rb;
             U += dU;
         }
