@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
 static constexpr int RD_P = 52;     // tile side
 static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
-static constexpr int RD_MAXA = 16;  // angles per group
+static constexpr int RD_MAXA = 24;  // at most this many angles per group
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
 static_assert(RD_P + 1 < 62, "pixel lanes (and lane RD_P, past the tile) stay clear of the discard lanes 62, 63");
 
@@ -976,15 +976,31 @@ __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int
         store_tile_transposed<T, 1024>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
 }
 
-// Angle groups of the ray-driven backprojector: enough blocks for two per
-// compute unit, at most RD_MAXA angles per group.
+// Angle groups of the ray-driven backprojector (one block per tile and
+// group), chosen once per operator.
 int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op) {
-    const int tiles = div_up(op->W, RD_P) * div_up(op->H, RD_P);
-    int G = div_up(op->joseph.n_ang, RD_MAXA);
-    const int want = div_up(2 * (ctx->n_cu > 0 ? ctx->n_cu : 256), tiles);
-    if (G < want) G = want;
-    if (G > op->joseph.n_ang) G = op->joseph.n_ang;
-    return G;
+    const JosephGeom& jg = op->joseph;
+    if (jg.rd_groups > 0) return jg.rd_groups;
+    // All blocks are resident at once, so the slowest compute unit sets the
+    // time: it runs ceil(tiles G / n_cu) blocks of ceil(n_ang / G) angles.
+    // Take the G with the least such load (the smallest on ties: fewer
+    // partial images to sum), with at most RD_MAXA angles per group.
+    const long long tiles = (long long)div_up(op->W, RD_P) * div_up(op->H, RD_P);
+    const long long ncu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+    const int na = jg.n_ang;
+    int best_g = na;
+    long long best = -1;
+    for (int G = div_up(na, RD_MAXA); G <= na; ++G) {
+        const long long load = ((tiles * G + ncu - 1) / ncu) * div_up(na, G);
+        if (best < 0 || load < best) {
+            best = load;
+            best_g = G;
+        }
+        if ((tiles * G + ncu - 1) / ncu > 4 * ((tiles * div_up(na, RD_MAXA) + ncu - 1) / ncu) + 8)
+            break;  // far past the point where more groups can help
+    }
+    jg.rd_groups = best_g;
+    return best_g;
 }
 
 template <typename T>

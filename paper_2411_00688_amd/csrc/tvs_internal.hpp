@@ -134,6 +134,8 @@ struct JosephGeom {
     // the ray-driven float32 backprojector applies (joseph_rd_angle_ok for
     // every angle)
     bool rd_ok = false;
+    // angle groups of the ray-driven backprojector, chosen on first use
+    mutable int rd_groups = 0;
 };
 
 struct BlurGeom {
