@@ -530,7 +530,7 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.small = (size_t)op->H * a.x_ld * sizeof(T) < (1ull << 32) &&
               (size_t)op->W * a.xT_ld * sizeof(T) < (1ull << 32);
     dim3 grid(div_up(a.n_det, 64), op->joseph.n_ang);
-    hipLaunchKernelGGL((joseph_fwd_kernel<T, 4>), grid, dim3(256), 0, ctx->stream, a);
+    hipLaunchKernelGGL((joseph_fwd_kernel<T, 8>), grid, dim3(512), 0, ctx->stream, a);
     TVS_LAUNCH_CHECK();
 }
 
