@@ -758,10 +758,10 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
 // (wavefront, angle) the 64 lanes take 64 consecutive rays that include every
 // ray reaching the wavefront's strip; a lane keeps its ray, its sinogram value
 // and its exact 32.32 position (one 64-bit add per step) for all 13 steps.
-// Per step the ray lanes scatter their two weights into a per-wavefront LDS
-// line of the strip's 52 pixels (distinct rays land on distinct slots, so no
-// atomics and no bank conflicts) and the pixel lanes read their totals into
-// registers.  Row-stepping sums are held per (row, lane = column),
+// Per step the ray lanes hand their two weights to the pixel lanes of the
+// strip's 52 pixels with forward permutes (distinct rays never share a
+// destination lane; no LDS memory is involved) and the pixel lanes add them
+// into registers.  Row-stepping sums are held per (row, lane = column),
 // column-stepping ones per (column, lane = row) and meet through an LDS
 // transpose, so every pixel's sum has one fixed order.  Each block writes its
 // group's partial image; joseph_adj_sum adds the G partials in order and
