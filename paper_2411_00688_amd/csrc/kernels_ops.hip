@@ -966,7 +966,17 @@ __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int
     if (i < H && j < W) {
         const size_t gi = (size_t)i * W + j;
         T s = part[gi];
-        for (int k = 1; k < G; ++k) s += part[(size_t)k * plane + gi];
+        // partials 1 .. G-1 in order, eight loads in flight at a time (a
+        // plain loop over the runtime G waits for each load before the next)
+        for (int k = 1; k < G; k += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = (k + u < G) ? part[(size_t)(k + u) * plane + gi] : T(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k + u < G) s += v[u];
+        }
         if (has_ps)
             s_t[li][lj] = primal_step(ps, gi, i, j, s);
         else
