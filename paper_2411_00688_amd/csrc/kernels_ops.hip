@@ -899,6 +899,7 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     __shared__ float yS[RD_MAXA][RD_NB];
     __shared__ int wst[RD_MAXA];
     __shared__ int ecls[RD_MAXA];
+    __shared__ float wgtS[RD_MAXA];
     __shared__ int eD[RD_MAXA][4];
     __shared__ long long eK[RD_MAXA][4];
     __shared__ float tileT[RD_P][RD_P + 1];
@@ -915,18 +916,31 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
         const JAngle& gg = a.ang[g + tid * G];
         wst[tid] = rd_window(gg, i0, j0);
         ecls[tid] = gg.cls;
+        wgtS[tid] = (float)gg.wgt;
     }
     if (tid < 4 * na_g) {
         const int m = tid >> 2, ww = tid & 3;
         rd_entry(a.ang[g + m * G], i0, j0, ww, eD[m][ww], eK[m][ww]);
     }
     __syncthreads();
-    for (int idx = tid; idx < na_g * RD_NB; idx += 256) {
-        const int m = idx / RD_NB, bb = idx - m * RD_NB;
-        const int d = wst[m] + bb;
-        const JAngle& gg = a.ang[g + m * G];
-        yS[m][bb] = (d >= 0 && d < a.n_det) ? (float)gg.wgt * a.y[(size_t)(g + m * G) * a.n_det + d]
-                                            : 0.0f;
+    // the group's sinogram windows, RD_MAXA * RD_NB / 256 loads per thread
+    // issued together (a loop over the runtime count would wait for each)
+    {
+        constexpr int NL = (RD_MAXA * RD_NB + 255) / 256;
+        float v[NL];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int idx = tid + 256 * r;
+            const int m = idx / RD_NB, bb = idx - m * RD_NB;
+            const int d = m < na_g ? wst[m] + bb : -1;
+            v[r] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int idx = tid + 256 * r;
+            const int m = idx / RD_NB, bb = idx - m * RD_NB;
+            if (m < na_g) yS[m][bb] = wgtS[m] * v[r];
+        }
     }
     __syncthreads();
     float accR[RD_L], accC[RD_L];
