@@ -417,6 +417,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
     const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
     const T* qy = f.q;
     const T* qx = f.q + plane;
+    // every load of the thread's four pixels first, then the arithmetic and
+    // the stores (loads after a store would wait for possible aliasing)
+    T qc_y[4], qc_x[4], qu[4], ql[4], vv[4], xh[4], hh[4], xo[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int li = idx / TW, lj = idx % TW;
+        const int i = i0 + li, j = j0 + lj;
+        const bool ok = i < H && j < W;
+        const size_t g = ok ? (size_t)i * W + j : 0;
+        qc_y[p] = ok ? qy[g] : T(0);
+        qc_x[p] = ok ? qx[g] : T(0);
+        qu[p] = ok && i > 0 ? qy[g - W] : T(0);
+        ql[p] = ok && j > 0 ? qx[g - 1] : T(0);
+        vv[p] = ok ? f.v[g] : T(0);
+        xh[p] = ok && f.mode != 0 ? f.xhat[g] : T(0);
+        hh[p] = ok && f.mode != 0 ? f.h[g] : T(0);
+        xo[p] = ok && f.mode == 2 ? f.x[g] : T(0);
+    }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int idx = (int)threadIdx.x + p * 256;
@@ -425,24 +444,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
         if (i >= H || j >= W) continue;
         const size_t g = (size_t)i * W + j;
         T d = T(0);
-        if (i < H - 1) d += qy[g];
-        if (i > 0) d -= qy[g - W];
-        if (j < W - 1) d += qx[g];
-        if (j > 0) d -= qx[g - 1];
-        T z = f.v[g] + d;
+        if (i < H - 1) d += qc_y[p];
+        if (i > 0) d -= qu[p];
+        if (j < W - 1) d += qc_x[p];
+        if (j > 0) d -= ql[p];
+        T z = vv[p] + d;
         if (f.nonneg) z = (z > T(0)) ? z : T(0);
         if (f.q_out != f.q) {
-            f.q_out[g] = qy[g];
-            f.q_out[plane + g] = qx[g];
+            f.q_out[g] = qc_y[p];
+            f.q_out[plane + g] = qc_x[p];
         }
         if (f.mode == 0) {
             f.z[g] = z;
         } else {
-            const T xh = f.xhat[g];
-            f.h[g] = f.h[g] + f.rate * (z - xh);
+            f.h[g] = hh[p] + f.rate * (z - xh[p]);
             if (f.mode == 2) {
-                const T xo = f.x[g];
-                const T xb = T(2) * z - xo;
+                const T xb = T(2) * z - xo[p];
                 f.xbar[(size_t)i * f.xbar_ld + j] = xb;
                 s_t[li][lj] = xb;
             }
