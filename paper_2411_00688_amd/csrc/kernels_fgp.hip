@@ -501,6 +501,22 @@ __global__ __launch_bounds__(256) void finalize_batched_kernel(const BSlice<T>* 
     const size_t off = (size_t)S.off, plane = (size_t)H * W;
     const T* qy = q + 2 * off;
     const T* qx = qy + plane;
+    // all loads of the thread's four pixels before its stores
+    T qc_y[4], qc_x[4], qu[4], ql[4], vv[4], xh[4], hh[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int idx = (int)threadIdx.x + p * 256;
+        const int i = i0 + idx / 32, j = j0 + idx % 32;
+        const bool ok = i < H && j < W;
+        const size_t g = ok ? (size_t)i * W + j : 0;
+        qc_y[p] = ok ? qy[g] : T(0);
+        qc_x[p] = ok ? qx[g] : T(0);
+        qu[p] = ok && i > 0 ? qy[g - W] : T(0);
+        ql[p] = ok && j > 0 ? qx[g - 1] : T(0);
+        vv[p] = ok ? v[off + g] : T(0);
+        xh[p] = ok ? xhat[off + g] : T(0);
+        hh[p] = ok ? h[off + g] : T(0);
+    }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int idx = (int)threadIdx.x + p * 256;
@@ -508,17 +524,17 @@ __global__ __launch_bounds__(256) void finalize_batched_kernel(const BSlice<T>* 
         if (i >= H || j >= W) continue;
         const size_t g = (size_t)i * W + j;
         T d = T(0);
-        if (i < H - 1) d += qy[g];
-        if (i > 0) d -= qy[g - W];
-        if (j < W - 1) d += qx[g];
-        if (j > 0) d -= qx[g - 1];
-        T z = v[off + g] + d;
+        if (i < H - 1) d += qc_y[p];
+        if (i > 0) d -= qu[p];
+        if (j < W - 1) d += qc_x[p];
+        if (j > 0) d -= ql[p];
+        T z = vv[p] + d;
         if (nonneg) z = (z > T(0)) ? z : T(0);
         if (q_out != q) {
-            q_out[2 * off + g] = qy[g];
-            q_out[2 * off + plane + g] = qx[g];
+            q_out[2 * off + g] = qc_y[p];
+            q_out[2 * off + plane + g] = qc_x[p];
         }
-        h[off + g] = h[off + g] + S.rate * (z - xhat[off + g]);
+        h[off + g] = hh[p] + S.rate * (z - xh[p]);
         x[off + g] = z;
     }
 }
