@@ -771,7 +771,7 @@ static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 24;  // at most this many angles per group
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
-static_assert(RD_P + 1 < 62, "pixel lanes (and lane RD_P, past the tile) stay clear of the discard lanes 62, 63");
+static_assert(RD_P + 1 < 62, "the lanes past the strip (RD_P, RD_P + 1, 62, 63) are no pixel lanes");
 
 // The ray-driven path applies to an angle when rays are at least a pixel
 // apart along the interpolation axis, the rays of a tile fit the staged
@@ -828,17 +828,14 @@ __device__ __forceinline__ long long wave_uniform64(long long v) {
 }
 
 // Permute byte addresses of one step: (1 - f) val goes to pixel lane h - 1,
-// f val to pixel lane h, with h the high word of U; rays outside the strip
-// push to lanes 62 and 63, which are no pixels (h - 1 = -1 wraps to 63 too;
-// the permute takes the lane modulo 64).
+// f val to pixel lane h, with h the high word of U (h - 1 = -1 wraps to lane
+// 63: the permute takes the lane modulo 64).  h is clamped into [-1, RD_P + 1]
+// first: a ray outside the strip then pushes to lanes 62 and 63 or RD_P and
+// RD_P + 1, none of which is a pixel of the strip, so no range test is needed.
 __device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
-    const bool in = (unsigned long long)U < ((unsigned long long)(RD_P + 1) << 32);
-    const unsigned hw = (unsigned)((unsigned long long)U >> 32);
-    int h4;
-    // 4 h as one shift of the high word (the compiler would form it as a
-    // 64-bit funnel shift and a mask)
-    __asm__("v_lshlrev_b32 %0, 2, %1" : "=v"(h4) : "v"(hw));
-    db = in ? h4 : 4 * 63;
+    int h = (int)(U >> 32);
+    h = h < -1 ? -1 : (h > RD_P + 1 ? RD_P + 1 : h);
+    db = 4 * h;
     da = db - 4;
 }
 
