@@ -507,7 +507,9 @@ def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
     Reports (i) cold prox calls: duality gap after the method's 50 FGP
     iterations from the zero dual and from the network's dual, and the FGP
     iterations the network's start needs to match the zero start; (ii)
-    PDHGSkip-2 with the gap-gated learned prox (gate 1e-3) to 1e-4."""
+    PDHGSkip-2 with the gap-gated learned prox (gate 1e-3) to 1e-4: the
+    iterations from an instrumented run, the time of an un-instrumented one
+    (HIP graph) of exactly that many."""
     import numpy as np
     import torch
     import synth
@@ -573,15 +575,34 @@ def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
     if phis:
         x = torch.zeros(N, N, device=dev)
         h, q, y = torch.zeros_like(x), torch.zeros(2, N, N, device=dev), torch.zeros(na, nd, device=dev)
-        r = T.tvs_pdhgskip_ex(op, b, x, h, q, y, w.alpha, sigma, tau, p, w.outer_iters, Kin,
-                              nonneg=1, seed=seed, want_obj=True, cnn=cnn, gap_tol=1e-3)
+
+        def solve(iters, obj=False):
+            for t in (x, h, q, y):
+                t.zero_()
+            return T.tvs_pdhgskip_ex(op, b, x, h, q, y, w.alpha, sigma, tau, p, iters, Kin,
+                                     nonneg=1, seed=seed, want_obj=obj, graph=not obj,
+                                     cnn=cnn, gap_tol=1e-3)
+
+        r = solve(w.outer_iters, obj=True)
         rel = np.abs(r["obj"] - phis) / phis
         bad = np.nonzero(rel > 1e-4)[0]
         kstar = int(bad[-1] + 2) if len(bad) else 1
-        res["pdhgskip_learned_gate_1e-3"] = {
-            "iters_to_1e-4": kstar if kstar <= w.outer_iters else None,
-            "final_rel": float(rel[-1]), "prox_calls": int(r["n_prox"]),
-            "fgp_fallbacks": int(r["n_fallback"])}
+        out = {"iters_to_1e-4": kstar if kstar <= w.outer_iters else None,
+               "final_rel": float(rel[-1]), "prox_calls": int(r["n_prox"]),
+               "fgp_fallbacks": int(r["n_fallback"])}
+        if kstar <= w.outer_iters:
+            times = []
+            for _ in range(3):
+                solve(kstar)  # capture / warm
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solve(kstar)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            out["ms_to_1e-4"] = round(float(np.median(times)), 3)
+        res["pdhgskip_learned_gate_1e-3"] = out
     T.tvs_cnn_destroy(cnn)
     return res
 

@@ -403,12 +403,12 @@ tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
 /* Learned prox of one H x W image with a duality-gap gate: the network's
  * dual q = P_lam(qt) is written to q_out [2][H][W]; if its relative gap
  * gap(q) / P(z_q) (the gap of eq. (6) in the form gap(q) = sum_i lam
- * |(D z_q)_i| - <(D z_q)_i, q_i>, P the prox objective) exceeds gap_tol and
- * fallback_iters > 0, FGP runs fallback_iters iterations warm-started from q
- * and q_out gets its final dual.  z_out gets P_X(v + div q_out).
- * fell_back_out (nullable) is set to 1 when FGP ran; rel_gap_out (nullable)
- * gets the network's relative gap.  Synchronises (the gate is decided on the
- * host). */
+ * |(D z_q)_i| - <(D z_q)_i, q_i>, P the prox objective) exceeds gap_tol
+ * (or is NaN) and fallback_iters > 0, FGP runs fallback_iters iterations
+ * warm-started from q and q_out gets its final dual.  z_out gets
+ * P_X(v + div q_out).  fell_back_out (nullable) is set to 1 when FGP ran;
+ * rel_gap_out (nullable) gets the network's relative gap.  Synchronises
+ * (the gate is decided on the host). */
 tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, int nonneg,
                         double gap_tol, int fallback_iters, float* q_out, float* z_out,
                         int* fell_back_out, double* rel_gap_out);
@@ -417,10 +417,12 @@ tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, 
  * tvs_solve_ext (NULL: the plain call):
  *  - cnn != NULL: every prox call of the run is the learned prox with the
  *    duality-gap gate of tvs_cnn_prox, decided on the device (so the run
- *    stays one HIP graph with TVS_FLAG_GRAPH): q <- P_lam(qt) from the
- *    network; if its relative gap exceeds gap_tol, params->inner_iters FGP
- *    iterations warm-started from it.  The network's dual replaces the warm
- *    dual of the previous call.  float32 only (TVS_ERR_UNSUPPORTED else).
+ *    stays one HIP graph with TVS_FLAG_GRAPH): the network's dual P_lam(qt)
+ *    becomes the call's dual when its relative gap is at most gap_tol;
+ *    otherwise params->inner_iters FGP iterations run, warm-started from
+ *    whichever of the network's dual and the previous call's dual (the warm
+ *    dual the plain run reuses) has the smaller relative gap.  A NaN gap
+ *    falls back.  float32 only (TVS_ERR_UNSUPPORTED else).
  *  - v_record != NULL: the prox inputs v (the argument of the prox in
  *    Alg. "ProxSkip" / "PDHGSkip-2") of the first max_record prox calls are
  *    copied to v_record (device, dtype, max_record x H x W), the pairs that

@@ -317,6 +317,8 @@ void prepare_solver_prox(tvs_cnn* c, int H, int W, double lam) {
         if (!c->fast) grow(c, tvs_cnn::B_X1L + l, npx * 64);
     }
     scratch(c->ctx, S_Z, npx * sizeof(float));
+    scratch(c->ctx, S_QNET, 2 * npx * sizeof(float));
+    scratch(c->ctx, S_SEL, sizeof(int));
     reserve_reduce_scratch(c->ctx, npx);
 }
 
@@ -324,23 +326,30 @@ float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam,
                            double tol, int iters, float* q, const FgpConfig& cfg, int* record) {
     tvs_ctx* ctx = c->ctx;
     const size_t npx = (size_t)H * W;
-    forward_convs(c, 1, H, W, v, q, 1, !c->fast);  // q <- P_lam(qt)
-    // relative duality gap of the network's dual (the standalone gap path)
+    float* qn = (float*)scratch(ctx, S_QNET, 2 * npx * sizeof(float));
+    forward_convs(c, 1, H, W, v, qn, 1, !c->fast);  // qn <- P_lam(qt)
+    // relative duality gaps of the network's dual (red[0], red[1]) and of the
+    // previous call's dual still in q (red[2], red[3])
     float* z = (float*)scratch(ctx, S_Z, npx * sizeof(float));
-    Finalize<float> f{};
-    f.v = v;
-    f.q = q;
-    f.q_out = q;
-    f.z = z;
-    f.nonneg = nonneg;
-    f.mode = 0;
-    launch_finalize<float>(ctx, H, W, f);
     double* red = (double*)scratch(ctx, S_RED, 8 * sizeof(double));
-    reduce_gap<float>(ctx, H, W, v, z, q, lam, red + 0, red + 1);
+    float* cand[2] = {qn, q};
+    for (int i = 0; i < 2; ++i) {
+        Finalize<float> f{};
+        f.v = v;
+        f.q = cand[i];
+        f.q_out = cand[i];
+        f.z = z;
+        f.nonneg = nonneg;
+        f.mode = 0;
+        launch_finalize<float>(ctx, H, W, f);
+        reduce_gap<float>(ctx, H, W, v, z, cand[i], lam, red + 2 * i, red + 2 * i + 1);
+    }
     int* flag = record;  // the per-call record doubles as this call's flag
-    launch_gate(ctx, red, tol, flag, nullptr);
+    int* sel = (int*)scratch(ctx, S_SEL, sizeof(int));
+    launch_gate(ctx, red, tol, flag, sel);
+    launch_copy_if(ctx, 2 * npx, sel, 1, qn, q);  // start (or result): the network's dual
     float* qf = run_fgp<float>(ctx, H, W, v, lam, iters, nonneg, q, cfg, flag);
-    if (qf != q) launch_copy_if_off(ctx, 2 * npx, flag, q, qf);
+    if (qf != q) launch_copy_if(ctx, 2 * npx, flag, 0, q, qf);
     return qf;
 }
 
@@ -500,7 +509,7 @@ extern "C" tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, d
         double g = 0, pr = 0;
         gap_host<float>(cnn->ctx, H, W, v, lam, nn, q_out, &g, &pr);
         const double rel = pr > 0 ? g / pr : g;
-        const bool fb = rel > gap_tol && fallback_iters > 0;
+        const bool fb = !(rel <= gap_tol) && fallback_iters > 0;  // a NaN gap falls back
         tv_prox_impl<float>(cnn->ctx, H, W, v, lam, fb ? fallback_iters : 0, nn, q_out, z_out,
                             nullptr);
         if (fell_back_out) *fell_back_out = fb ? 1 : 0;

@@ -525,22 +525,25 @@ __global__ void pack_weights_kernel(const float* w, int cin, int cout, int coutp
 }
 
 // ------------------------------------------------------------------ gate
-// flag = [relative duality gap > tol], from the two sums of the gap
-// reduction (gap, primal value); record (nullable) keeps the decision.
-__global__ void gate_kernel(const double* red, double tol, int* flag, int* record) {
+// Gate of a learned prox call inside a solver run.  red[0], red[1]: gap and
+// primal value at the network's dual; red[2], red[3]: the same at the
+// previous call's dual.  flag = 0 when the network's relative gap is at most
+// tol (its dual is the result), else 1 (FGP runs; a NaN gap falls back too).
+// sel = 1 when the network's dual is the result or FGP's start: gate open,
+// or a relative gap below the previous dual's.
+__global__ void gate_kernel(const double* red, double tol, int* flag, int* sel) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const double gap = red[0], primal = red[1];
-        const double rel = primal > 0.0 ? gap / primal : gap;
-        const int f = rel > tol ? 1 : 0;
+        const double rn = red[1] > 0.0 ? red[0] / red[1] : red[0];
+        const double rp = red[3] > 0.0 ? red[2] / red[3] : red[2];
+        const int f = rn <= tol ? 0 : 1;
         flag[0] = f;
-        if (record) record[0] = f;
+        sel[0] = (f == 0 || rn < rp) ? 1 : 0;
     }
 }
 
-// dst = src where the gate is off (FGP did not run, so its output buffer
-// must receive the network's dual)
-__global__ void copy_if_off_kernel(size_t n, const int* flag, const float* src, float* dst) {
-    if (*flag != 0) return;
+// dst = src where (*flag != 0) == (when != 0)
+__global__ void copy_if_kernel(size_t n, const int* flag, int when, const float* src, float* dst) {
+    if ((*flag != 0) != (when != 0)) return;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -660,15 +663,16 @@ void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, 
     TVS_LAUNCH_CHECK();
 }
 
-void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* record) {
-    gate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, flag, record);
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* sel) {
+    gate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, flag, sel);
     TVS_LAUNCH_CHECK();
 }
 
-void launch_copy_if_off(tvs_ctx* ctx, size_t n, const int* flag, const float* src, float* dst) {
+void launch_copy_if(tvs_ctx* ctx, size_t n, const int* flag, int when, const float* src,
+                    float* dst) {
     size_t b = (n + 255) / 256;
     const size_t cap = (size_t)ctx->n_cu * 8;
-    copy_if_off_kernel<<<(int)(b < cap ? b : cap), 256, 0, ctx->stream>>>(n, flag, src, dst);
+    copy_if_kernel<<<(int)(b < cap ? b : cap), 256, 0, ctx->stream>>>(n, flag, when, src, dst);
     TVS_LAUNCH_CHECK();
 }
 

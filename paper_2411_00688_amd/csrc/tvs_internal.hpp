@@ -51,7 +51,7 @@ struct Scratch {
 enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
     S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
-    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_COUNT
+    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_QNET, S_SEL, S_COUNT
 };
 
 struct GraphEntry;
@@ -404,14 +404,16 @@ void launch_adam(tvs_ctx* ctx, int n, float* p, const float* grad, float* m, flo
                  float b1, float b2, float c1, float c2, float eps);
 void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, uint16_t* wf_lo,
                  uint16_t* wb);
-void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* record);
-void launch_copy_if_off(tvs_ctx* ctx, size_t n, const int* flag, const float* src, float* dst);
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* sel);
+void launch_copy_if(tvs_ctx* ctx, size_t n, const int* flag, int when, const float* src,
+                    float* dst);
 // Learned prox inside a solver run (capturable): allocations and lam set up
-// by prepare_solver_prox before capture; enqueue_solver_prox writes
-// P_lam(net(v)) into q, gates on its relative duality gap (device side) and
-// runs `iters` FGP iterations warm-started from it when the gap is above
-// tol.  Returns the buffer holding the final dual; *record (device) gets 1
-// if FGP ran.
+// by prepare_solver_prox before capture; enqueue_solver_prox computes
+// P_lam(net(v)) and gates on its relative duality gap (device side): at most
+// tol, it becomes the dual; above, `iters` FGP iterations run, warm-started
+// from whichever of it and the previous call's dual in q has the smaller
+// relative gap.  Returns the buffer holding the final dual; *record (device)
+// gets 1 if FGP ran.
 void prepare_solver_prox(tvs_cnn* c, int H, int W, double lam);
 bool fast_forward(const tvs_cnn* c);
 float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam, int nonneg,

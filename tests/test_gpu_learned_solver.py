@@ -8,8 +8,9 @@ recording (tvs_proxskip_ex / tvs_pdhgskip_ex).
   always open every prox call returns P_X(v): the run equals the plain run
   with alpha = 0 bit for bit.
 - With the gate always closed, every call runs inner_iters FGP iterations
-  from that zero dual: the run equals the oracle stepped one iteration at a
-  time with the warm dual reset to zero before each step.
+  from the zero network dual or the previous call's dual, whichever has the
+  smaller relative gap: the run equals the oracle stepped one iteration at a
+  time with that choice made in float64 before each prox call.
 """
 import numpy as np
 import pytest
@@ -96,24 +97,40 @@ def test_zero_network_gate_open_equals_alpha_zero(ctx, zero_cnn, graph):
         T.tvs_op_destroy(op)
 
 
-def test_zero_network_gate_closed_is_cold_fgp(ctx, zero_cnn):
+def test_zero_network_gate_closed_starts_from_better_dual(ctx, zero_cnn):
     N = 40
     _, b = denoise_problem(N, dtype=F32)
     K, Kin, p, seed, alpha = 30, 15, 0.4, 8, 0.1
+    lam = alpha / p  # step 1
+    # a poor initial dual: the first call must start from the network's zero
+    q0 = as_input(np.random.default_rng(4).uniform(-lam, lam, (2, N, N)), F32)
     op = T.tvs_op_identity(ctx, N, N)
     try:
-        x, h, q = zeros((N, N)), zeros((N, N)), zeros((2, N, N))
+        x, h, q = zeros((N, N)), zeros((N, N)), dev(q0, F32)
         r = T.tvs_proxskip_ex(op, dev(b, F32), x, h, q, alpha, 1.0, p, K, Kin, seed=seed,
                               cnn=zero_cnn, gap_tol=-1.0, want_theta=True)
         assert r["n_fallback"] == r["n_prox"] > 0
         A = O.identity(N, N)
-        xo, ho = np.zeros((N, N)), np.zeros((N, N))
+        xo, ho, qo = np.zeros((N, N)), np.zeros((N, N)), q0.astype(np.float64)
+        starts = []
         for k in range(K):
-            ref = O.proxskip(A, b, alpha, 1.0, p, 1, Kin, seed=seed, k0=k, x=xo, h=ho,
-                             q=np.zeros((2, N, N)))
-            xo, ho = ref["x"], ref["h"]
+            start = qo
+            if r["theta"][k]:
+                v = (xo - (xo - b)) + (1.0 - 1.0 / p) * ho  # the prox argument at step 1
+                rel = []
+                for cand in (np.zeros((2, N, N)), qo):
+                    g, pr = O.tv_gap(v, lam, cand)
+                    rel.append(g / pr if pr > 0 else g)
+                # a clear margin, so float32 gaps take the same decision
+                assert abs(rel[0] - rel[1]) > 1e-3 * max(rel), (k, rel)
+                start = np.zeros((2, N, N)) if rel[0] < rel[1] else qo
+                starts.append(rel[0] < rel[1])
+            ref = O.proxskip(A, b, alpha, 1.0, p, 1, Kin, seed=seed, k0=k, x=xo, h=ho, q=start)
+            xo, ho, qo = ref["x"], ref["h"], ref["q"]
+        assert starts[0] and not all(starts)  # both starts are exercised
         assert rel_l2(host(x), xo) < 1e-4
         assert rel_l2(host(h), ho) < 1e-3
+        assert rel_l2(host(q), qo) < 1e-3
     finally:
         T.tvs_op_destroy(op)
 
