@@ -340,9 +340,9 @@ def fgp_hbm(T, ctx, n, Kin):
     """FGP at n x n float32 (working set far beyond the 256 MB last-level
     cache): a one-iteration-per-launch variant moves exactly the algorithmic
     28 B/px (read q_{k-1}, q_{k-2}, v; write q_k), so its GB/s is an HBM rate
-    (the faster of the two such tile shapes is reported, next to a plain
-    device copy's rate on the same GPU); the tuned temporally blocked variant
-    is reported as an effective rate."""
+    (the fastest such variant, tiles or row-walking strips, is reported next
+    to torch's 1 GiB device copy on the same GPU); the tuned temporally
+    blocked variant is reported as an effective rate."""
     import torch
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev).manual_seed(1)

@@ -184,12 +184,153 @@ __device__ __forceinline__ void fgp_tile(const FgpArgs<T>& a, int ty, int tx) {
     }
 }
 
+// One FGP iteration (nsteps == 1) on a strip of 256 columns and RC rows,
+// walked down row by row: thread t owns column j0 + t, so every load and
+// store is one aligned, contiguous row segment and rows are read once (no
+// halo rows; the strip's side halo is one column each way, loaded by the
+// edge threads).  Step i forms r at row i and z at row i (its up term is
+// r_y of row i-1, kept in a register; its left term r_x of the left
+// neighbour, through LDS) and then finishes q at row i-1, which needs z at
+// rows i-1 and i and at the right neighbour of row i-1 (from the previous
+// step's LDS row).  Double-buffered LDS rows leave one barrier per row.  The
+// operands of the next row are in flight while a row is computed.  The
+// per-pixel arithmetic and its order are those of fgp_tile, so results are
+// bitwise identical.
+template <typename T, int RC>
+__device__ __forceinline__ void fgp_strip(const FgpArgs<T>& a, int ty, int tx) {
+    constexpr int SW = 256;
+    __shared__ T s_rx[2][SW + 1];  // [0]: left halo column, [t + 1]: thread t
+    __shared__ T s_z[2][SW + 1];   // [t]: thread t, [SW]: right halo column
+    const int H = a.H, W = a.W;
+    const int tid = (int)threadIdx.x;
+    const int j0 = tx * SW, j = j0 + tid, jr = j0 + SW;
+    const int ib = ty * RC;
+    const int ie = (ib + RC < H) ? ib + RC : H;  // output rows [ib, ie)
+    const bool col = j < W;
+    const bool hl = tid == 0 && j0 > 0;        // loads r_x of column j0 - 1
+    const bool hr = tid == SW - 1 && jr < W;   // loads column jr
+    const T* qay = a.qa;
+    const T* qax = a.qa + a.plane;
+    const T* qby = a.qb;
+    const T* qbx = a.qb + a.plane;
+    const T beta = a.beta[a.k_start];
+    const T lam = a.lam;
+    const T eighth = T(0.125);
+    auto rf = [&](T qa_, T qb_) { return qa_ + beta * (qa_ - qb_); };
+
+    // r_y of row ib - 1 (the up term of z at row ib)
+    T ry_up = T(0), ryh_up = T(0);
+    if (ib > 0) {
+        const size_t g = (size_t)(ib - 1) * W;
+        if (col) ry_up = rf(qay[g + j], qby[g + j]);
+        if (hr) ryh_up = rf(qay[g + jr], qby[g + jr]);
+    }
+    // operands of a row: own column, right halo column (h*), left halo (l*)
+    struct Row {
+        T ay, ax, by, bx, v, hay, hax, hby, hbx, hv, lax, lbx;
+    };
+    auto load_row = [&](int i) {
+        Row r{};
+        if (i >= H) return r;
+        const size_t g = (size_t)i * W;
+        if (col) {
+            r.ay = qay[g + j];
+            r.ax = qax[g + j];
+            r.by = qby[g + j];
+            r.bx = qbx[g + j];
+            r.v = a.v[g + j];
+        }
+        if (hr) {
+            r.hay = qay[g + jr];
+            r.hax = qax[g + jr];
+            r.hby = qby[g + jr];
+            r.hbx = qbx[g + jr];
+            r.hv = a.v[g + jr];
+        }
+        if (hl) {
+            r.lax = qax[g + j0 - 1];
+            r.lbx = qbx[g + j0 - 1];
+        }
+        return r;
+    };
+    Row nx = load_row(ib);  // row i + 1 is in flight while row i is computed
+    T ry_p = T(0), rx_p = T(0), z_p = T(0);  // row i - 1
+    for (int i = ib; i <= ie; ++i) {
+        const int b = (i - ib) & 1;
+        const bool row = i < H;
+        const Row c = nx;
+        if (i < ie) nx = load_row(i + 1);
+        const T ay = c.ay, ax = c.ax, by = c.by, bx = c.bx, vv = c.v;
+        const T hay = c.hay, hax = c.hax, hby = c.hby, hbx = c.hbx, hv = c.hv;
+        const T lax = c.lax, lbx = c.lbx;
+        const bool in = row && col;
+        const T ry = in ? rf(ay, by) : T(0);
+        const T rx = in ? rf(ax, bx) : T(0);
+        const bool hin = row && hr;
+        const T ryh = hin ? rf(hay, hby) : T(0);
+        const T rxh = hin ? rf(hax, hbx) : T(0);
+        s_rx[b][tid + 1] = rx;
+        if (tid == 0) s_rx[b][0] = (row && hl) ? rf(lax, lbx) : T(0);
+        __syncthreads();
+        // z = P_X(v + div r) at row i
+        T z = T(0);
+        if (in) {
+            T d = T(0);
+            if (i < H - 1) d += ry;
+            if (i > 0) d -= ry_up;
+            if (j < W - 1) d += rx;
+            if (j > 0) d -= s_rx[b][tid];
+            z = vv + d;
+            if (a.nonneg) z = (z > T(0)) ? z : T(0);
+        }
+        s_z[b][tid] = z;
+        if (tid == SW - 1) {
+            T zh = T(0);
+            if (hin) {
+                T d = T(0);
+                if (i < H - 1) d += ryh;
+                if (i > 0) d -= ryh_up;
+                if (jr < W - 1) d += rxh;
+                d -= rx;  // jr > 0: the left neighbour is this thread's column
+                zh = hv + d;
+                if (a.nonneg) zh = (zh > T(0)) ? zh : T(0);
+            }
+            s_z[b][SW] = zh;
+        }
+        // q = P_lambda(r + D z / 8) at row i - 1
+        if (i > ib && col) {
+            const int o = i - 1;
+            const T gy = (o < H - 1) ? z - z_p : T(0);
+            const T gx = (j < W - 1) ? s_z[b ^ 1][tid + 1] - z_p : T(0);
+            const T wy = ry_p + eighth * gy;
+            const T wx = rx_p + eighth * gx;
+            const T sc = ball_scale<T>(wy, wx, lam);
+            const size_t g = (size_t)o * W + j;
+            a.oa[g] = wy * sc;
+            a.oa[a.plane + g] = wx * sc;
+        }
+        ry_up = ry;
+        ryh_up = ryh;
+        ry_p = ry;
+        rx_p = rx;
+        z_p = z;
+    }
+}
+
 template <typename T, int BW, int BH, int TS>
 __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
     if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
     const int gx = div_up(a.W, BW);
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     fgp_tile<T, BW, BH, TS>(a, t / gx, t % gx);
+}
+
+template <typename T, int RC>
+__global__ __launch_bounds__(256) void fgp_strip_kernel(FgpArgs<T> a) {
+    if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
+    const int gx = div_up(a.W, 256);
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    fgp_strip<T, RC>(a, t / gx, t % gx);
 }
 
 // Batched form: block b of the launch works on tile (b - prefix[i]) of slice
@@ -216,9 +357,11 @@ __device__ __forceinline__ int find_item(const int* prefix, int n, int b) {
     return lo;
 }
 
-template <typename T, int BW, int BH, int TS>
-__global__ __launch_bounds__(256) void fgp_tb_batched_kernel(FgpBatchArgs<T> a) {
-    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // one block per tile
+// The slice and tile (ty, tx) of block b of a batched launch with tiles
+// BW wide; returns the slice's arguments.
+template <typename T, int BW>
+__device__ __forceinline__ FgpArgs<T> batched_tile(const FgpBatchArgs<T>& a, int b, int& ty,
+                                                   int& tx) {
     const int i = find_item(a.prefix, a.n_act, b);
     const BSlice<T> sl = a.sl[a.act[i]];
     const int t = b - a.prefix[i];
@@ -234,19 +377,40 @@ __global__ __launch_bounds__(256) void fgp_tb_batched_kernel(FgpBatchArgs<T> a) 
     f.H = sl.H;
     f.W = sl.W;
     f.plane = (size_t)sl.H * sl.W;
-    fgp_tile<T, BW, BH, TS>(f, t / tiles_x, t % tiles_x);
+    ty = t / tiles_x;
+    tx = t % tiles_x;
+    return f;
+}
+
+template <typename T, int BW, int BH, int TS>
+__global__ __launch_bounds__(256) void fgp_tb_batched_kernel(FgpBatchArgs<T> a) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // one block per tile
+    int ty, tx;
+    const FgpArgs<T> f = batched_tile<T, BW>(a, b, ty, tx);
+    fgp_tile<T, BW, BH, TS>(f, ty, tx);
+}
+
+template <typename T, int RC>
+__global__ __launch_bounds__(256) void fgp_strip_batched_kernel(FgpBatchArgs<T> a) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int ty, tx;
+    const FgpArgs<T> f = batched_tile<T, 256>(a, b, ty, tx);
+    fgp_strip<T, RC>(f, ty, tx);
 }
 
 // ----------------------------------------------------------------- configs
 // Tile shapes compiled in; the autotuner (or the default) picks one by index.
 struct FgpVariant {
     int bw, bh, ts;
+    int strip = 0;  // 1: fgp_strip (bw 256, bh rows per block, ts 1)
 };
 static const FgpVariant kFgpVariants[] = {
     {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8},
     {64, 16, 1}, {64, 16, 4}, {64, 32, 4}, {16, 16, 4}, {64, 32, 8},
     // small images (latency-bound: fewer launches per prox call)
     {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2},
+    // one iteration per launch on row-walking strips (HBM-bound sizes)
+    {256, 8, 1, 1}, {256, 32, 1, 1},
 };
 
 template <typename T>
@@ -254,7 +418,7 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     const FgpVariant& V = kFgpVariants[vi];
     dim3 grid(div_up(a.W, V.bw) * div_up(a.H, V.bh));
 #define TVS_FGPV(BW_, BH_, TS_)                                                            \
-    if (V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                       \
+    if (!V.strip && V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                    \
         hipLaunchKernelGGL((fgp_tb_kernel<T, BW_, BH_, TS_>), grid, dim3(256), 0, st, a); \
         return;                                                                            \
     }
@@ -263,6 +427,14 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     TVS_FGPV(16, 16, 8) TVS_FGPV(32, 16, 4) TVS_FGPV(32, 16, 8) TVS_FGPV(16, 16, 2)
     if (sizeof(T) == 4) { TVS_FGPV(64, 32, 8) }
 #undef TVS_FGPV
+    const dim3 sgrid(div_up(a.W, 256) * div_up(a.H, V.bh));
+#define TVS_FGPS(RC_)                                                                  \
+    if (V.strip && V.bh == RC_) {                                                      \
+        hipLaunchKernelGGL((fgp_strip_kernel<T, RC_>), sgrid, dim3(256), 0, st, a); \
+        return;                                                                        \
+    }
+    TVS_FGPS(8) TVS_FGPS(32)
+#undef TVS_FGPS
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
 }
 
@@ -346,7 +518,7 @@ template <typename T>
 static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blocks, hipStream_t st) {
     const FgpVariant& V = kFgpVariants[vi];
 #define TVS_FGPB(BW_, BH_, TS_)                                                                  \
-    if (V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                             \
+    if (!V.strip && V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                          \
         hipLaunchKernelGGL((fgp_tb_batched_kernel<T, BW_, BH_, TS_>), dim3(blocks), dim3(256), 0, \
                            st, a);                                                               \
         return;                                                                                  \
@@ -356,6 +528,13 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
     TVS_FGPB(16, 16, 8) TVS_FGPB(32, 16, 4) TVS_FGPB(32, 16, 8) TVS_FGPB(16, 16, 2)
     if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
 #undef TVS_FGPB
+#define TVS_FGPS(RC_)                                                                            \
+    if (V.strip && V.bh == RC_) {                                                                \
+        hipLaunchKernelGGL((fgp_strip_batched_kernel<T, RC_>), dim3(blocks), dim3(256), 0, st, a); \
+        return;                                                                                  \
+    }
+    TVS_FGPS(8) TVS_FGPS(32)
+#undef TVS_FGPS
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
 }
 
