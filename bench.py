@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_TFLOPS = 157.3       # MI355X vector fp32
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 MFMA
+CNN_FLOP_PER_PX = 2 * 9 * (2 * 32 + 32 * 32 + 32 * 32 + 32 * 2)  # 3x3 convs 2-32-32-32-2
 
 
 def log(*a):
@@ -91,9 +93,10 @@ def main():
     if args.kernels_only:
         kern = kernel_times(T, ctx, op, N, na, nd, Kin, 0, K)
         fgp_big = fgp_hbm(T, ctx, args.fgp_size, Kin)
+        cnn_fwd = cnn_forward_rate(T, ctx)
         print(json.dumps({"record": "kernels", "launch_ms": kern["launch_ms"],
-                          "copy_calibration_bytes": COPY_CAL_BYTES, "tv_prox_hbm": fgp_big}),
-              flush=True)
+                          "copy_calibration_bytes": COPY_CAL_BYTES, "tv_prox_hbm": fgp_big,
+                          "cnn_forward": cnn_fwd}), flush=True)
         T.tvs_op_destroy(op)
         T.tvs_ctx_destroy(ctx)
         return
@@ -390,6 +393,28 @@ def fgp_hbm(T, ctx, n, Kin):
     return res
 
 
+def cnn_forward_rate(T, ctx, N=512, reps=20):
+    """The learned prox's network forward on one N x N image, both operand
+    modes: time per call (HIP events) and the MFMA rate.  Useful work is
+    CNN_FLOP_PER_PX per pixel; the two-part BF16 mode issues three MFMAs per
+    product (hi*hi, hi*lo, lo*hi), so its issued rate is three times that."""
+    import torch
+    dev = torch.device("cuda:0")
+    cnn = T.tvs_cnn_create(ctx, 7)
+    v = torch.rand(N, N, device=dev, generator=torch.Generator(device=dev).manual_seed(2))
+    qt = torch.empty(1, 2, N, N, device=dev)
+    res = {"size": N, "flop_per_px": CNN_FLOP_PER_PX}
+    for fast, name, mult in ((False, "bf16x3", 3), (True, "bf16x1", 1)):
+        T.tvs_cnn_set_fast_forward(cnn, fast)
+        ms = _evtime(lambda: T.tvs_cnn_forward(cnn, v, 0.43, 1, qt, None), reps)
+        tf = CNN_FLOP_PER_PX * N * N / (ms * 1e-3) / 1e12
+        res[name] = {"ms": round(ms, 4), "useful_TFLOP/s": round(tf, 1),
+                     "mfma_issued_TFLOP/s": round(mult * tf, 1),
+                     "frac_of_bf16_peak": round(mult * tf / PEAK_BF16_TFLOPS, 4)}
+    T.tvs_cnn_destroy(cnn)
+    return res
+
+
 def light_prox_bench(T, ctx):
     """ProxSkip on the light-prox problems (Sec. 2.1-2.2) on a 200 x 300
     shapes-like phantom with noise 0.05, float64, the paper's protocol:
@@ -566,6 +591,10 @@ def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
     per_it = (t_fgp - t_fin) / Kin
     res["ms"] = {"fgp_50": round(t_fgp, 4), "fgp_per_iter": round(per_it, 5),
                  "network_forward": fwd}
+    # MFMA rate of the forward (two-part mode issues three MFMAs per product)
+    res["network_forward_mfma_frac_of_bf16_peak"] = {
+        k: round((3 if k == "bf16x3" else 1) * CNN_FLOP_PER_PX * N * N / (ms * 1e-3) / 1e12
+                 / PEAK_BF16_TFLOPS, 4) for k, ms in fwd.items()}
     if match:
         res["cold_prox_ms_to_zero_start_gap"] = {
             "zero_start": round(t_fgp, 4),
