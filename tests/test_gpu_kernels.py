@@ -103,6 +103,38 @@ def test_fgp_tile_variants_agree_bitwise(ctx):
             assert np.array_equal(z, outs[0][0]) and np.array_equal(q, outs[0][1])
 
 
+def variant_index(shape):
+    for vi in range(T.tvs_fgp_variant_count()):
+        if T.tvs_fgp_variant(vi) == shape:
+            return vi
+    raise AssertionError(f"variant {shape} not compiled")
+
+
+@pytest.mark.parametrize("H,W", [(37, 600), (9, 513), (70, 256), (17, 257)])
+def test_fgp_strip_variants_span_strips(ctx, H, W):
+    """The row-walking strip variants (256 columns per workgroup) across
+    several strips: the halo columns between strips, a ragged last strip and
+    a ragged last row block give the tile variants' results bit for bit, in
+    both precisions, with and without the nonnegativity constraint."""
+    v = rng(11).standard_normal((H, W))
+    strips = [vi for vi in range(T.tvs_fgp_variant_count()) if T.tvs_fgp_variant(vi)[0] == 256]
+    assert strips
+    ref = variant_index((32, 32, 1))
+    for dt in (F64, F32):
+        kind = T.TVS_F64 if dt == F64 else T.TVS_F32
+        for nonneg in (0, 1):
+            outs = []
+            for vi in [ref] + strips:
+                T.tvs_fgp_set_variant(ctx, kind, H, W, vi)
+                q = torch.zeros(2, H, W, dtype=dt, device="cuda")
+                z = torch.empty(H, W, dtype=dt, device="cuda")
+                T.tvs_tv_prox(ctx, dev(v, dt), 0.2, 9, nonneg, q, z)
+                outs.append((host(z), host(q)))
+            T.tvs_fgp_set_variant(ctx, kind, H, W, -1)
+            for z, q in outs[1:]:
+                assert np.array_equal(z, outs[0][0]) and np.array_equal(q, outs[0][1]), (dt, nonneg)
+
+
 def test_tv_prox_identity_cases_bitwise(ctx):
     H, W = 70, 90
     v = rng(9).standard_normal((H, W))
