@@ -378,14 +378,22 @@ def fgp_hbm(T, ctx, n, Kin):
     res["one_iter_per_launch"]["frac_of_device_copy"] = round(
         res["one_iter_per_launch"]["GB/s"] / copy_gbs, 4)
     del a, b
-    # measured bytes per launch (rocprofv3 counters, while the kernel source is unchanged)
+    # the tuned variant's rate counts algorithmic bytes per iteration: effective
+    t = res["tuned"]
+    t["effective_GB/s"] = t.pop("GB/s")
+    t["effective_frac_of_hbm_peak"] = t.pop("frac_of_hbm_peak")
+    # measured bytes per launch (rocprofv3 counters, while the kernel source is
+    # unchanged) and the HBM rate they give at the launch's duration
     rec = measured_traffic("paper_2411_00688_amd/csrc/kernels_fgp.hip", "fgp_source_sha256")
     if rec and n == 8192:
         by = rec.get("fgp_8192_bytes_per_launch", {})
         for key in ("one_iter_per_launch", "tuned"):
             name = "x".join(str(x) for x in res[key]["variant"])
             if name in by:
-                res[key]["traffic_per_launch"] = by[name]
+                r = res[key]
+                r["traffic_per_launch"] = by[name]
+                launch_s = r["ms_per_iter"] * r["variant"][2] * 1e-3
+                r["measured_hbm_GB/s"] = round(by[name] / launch_s / 1e9, 1)
     T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, -1)
     del v, q, z
     torch.cuda.empty_cache()

@@ -317,6 +317,153 @@ __device__ __forceinline__ void fgp_strip(const FgpArgs<T>& a, int ty, int tx) {
     }
 }
 
+// TS iterations per launch on a strip of 256 columns walked down its rows
+// (TS >= 2): a pipeline of TS row-walking stages, stage s computing
+// iteration k + s - 1 and running two rows behind stage s - 1, whose output
+// row of the previous step it consumes, so all stages share one barrier
+// per row.  Momentum needs q_{k+s-3}: stage s - 2's output three steps
+// earlier (register histories).  Every stage loses one valid column on each
+// side, so strips overlap: a strip loads 256 columns and stores the middle
+// 256 - 2 TS; a block stores RC rows and reads RC + 2 TS.  A stage skips
+// (uniformly) the rows its successors do not need.  Per-pixel arithmetic
+// and order are those of fgp_tile: bitwise identical results.
+template <typename T, int RC, int TS>
+__device__ __forceinline__ void fgp_strip_tb(const FgpArgs<T>& a, int ty, int tx) {
+    constexpr int SW = 256, OW = SW - 2 * TS, NV = 2 * TS - 1;
+    __shared__ T s_rx[TS][2][SW + 1];  // [t + 1]: thread t, [0]: zero
+    __shared__ T s_z[TS][2][SW + 1];   // [t]: thread t, [SW]: zero
+    const int H = a.H, W = a.W;
+    const int tid = (int)threadIdx.x;
+    const int j = tx * OW - TS + tid;
+    const int ib = ty * RC;
+    const int ie = (ib + RC < H) ? ib + RC : H;  // stored rows [ib, ie)
+    const int i0 = ib - TS;                       // first row read
+    const int ns = a.nsteps;
+    const bool col = j >= 0 && j < W;
+    const bool ocol = col && tid >= TS && tid < SW - TS;
+    const T* qay = a.qa;
+    const T* qax = a.qa + a.plane;
+    const T* qby = a.qb;
+    const T* qbx = a.qb + a.plane;
+    const T lam = a.lam;
+    const T eighth = T(0.125);
+    if (tid < TS * 2) {
+        s_rx[tid >> 1][tid & 1][0] = T(0);
+        s_z[tid >> 1][tid & 1][SW] = T(0);
+    }
+    T beta[TS];
+#pragma unroll
+    for (int s = 0; s < TS; ++s) beta[s] = (s < ns) ? a.beta[a.k_start + s] : T(0);
+    // Ey/Ex[s][d]: stage s's output row of d + 1 steps ago (s = 0: the q_{k-1}
+    // row read then); qb1: the q_{k-2} row read one step ago; V[d]: v of d + 1
+    // steps ago; per stage: r_y of its previous row, that row's r and z.
+    T Ey[TS][3], Ex[TS][3], V[NV];
+    T ryup[TS], ryp[TS], rxp[TS], zp[TS];
+#pragma unroll
+    for (int s = 0; s < TS; ++s) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Ey[s][d] = Ex[s][d] = T(0);
+        ryup[s] = ryp[s] = rxp[s] = zp[s] = T(0);
+    }
+#pragma unroll
+    for (int d = 0; d < NV; ++d) V[d] = T(0);
+    T qby1 = T(0), qbx1 = T(0);
+    const int nsteps = (ie - ib) + 3 * TS;
+    for (int t = 0; t < nsteps; ++t) {
+        const int b = t & 1;
+        // the row read in this step is consumed in the next
+        T ly = T(0), lx = T(0), lby = T(0), lbx = T(0), lv = T(0);
+        const int li = i0 + t;
+        if (col && li >= 0 && li < H && li < ie + TS) {
+            const size_t g = (size_t)li * W + j;
+            ly = qay[g];
+            lx = qax[g];
+            lby = qby[g];
+            lbx = qbx[g];
+            lv = a.v[g];
+        }
+        T ry[TS], rx[TS];
+#pragma unroll
+        for (int s = 0; s < TS; ++s) {
+            const int m = i0 + t - 2 * s - 1;  // row of stage s + 1
+            const bool act = s < ns && m >= ib - TS + s && m < ie + TS - s;
+            const bool in = act && col && m >= 0 && m < H;
+            const T Ay = Ey[s][0], Ax = Ex[s][0];
+            const T By = (s == 0) ? qby1 : Ey[s - 1][2];
+            const T Bx = (s == 0) ? qbx1 : Ex[s - 1][2];
+            ry[s] = in ? Ay + beta[s] * (Ay - By) : T(0);
+            rx[s] = in ? Ax + beta[s] * (Ax - Bx) : T(0);
+            if (act) s_rx[s][b][tid + 1] = rx[s];
+        }
+        __syncthreads();
+        T ey[TS], ex[TS];
+#pragma unroll
+        for (int s = 0; s < TS; ++s) {
+            ey[s] = ex[s] = T(0);
+            const int m = i0 + t - 2 * s - 1;
+            const bool act = s < ns && m >= ib - TS + s && m < ie + TS - s;
+            if (!act) continue;
+            // z = P_X(v + div r) at row m
+            T z = T(0);
+            if (col && m >= 0 && m < H) {
+                T d = T(0);
+                if (m < H - 1) d += ry[s];
+                if (m > 0) d -= ryup[s];
+                if (j < W - 1) d += rx[s];
+                if (j > 0) d -= s_rx[s][b][tid];
+                z = V[2 * s] + d;
+                if (a.nonneg) z = (z > T(0)) ? z : T(0);
+            }
+            s_z[s][b][tid] = z;
+            // q = P_lambda(r + D z / 8) at row m - 1
+            const int o = m - 1;
+            if (col && o >= 0 && o < H) {
+                const T gy = (o < H - 1) ? z - zp[s] : T(0);
+                const T gx = (j < W - 1) ? s_z[s][b ^ 1][tid + 1] - zp[s] : T(0);
+                const T wy = ryp[s] + eighth * gy;
+                const T wx = rxp[s] + eighth * gx;
+                const T sc = ball_scale<T>(wy, wx, lam);
+                ey[s] = wy * sc;
+                ex[s] = wx * sc;
+                if (ocol && o >= ib && o < ie) {
+                    const size_t g = (size_t)o * W + j;
+                    if (s + 1 == ns) {
+                        a.oa[g] = ey[s];
+                        a.oa[a.plane + g] = ex[s];
+                    } else if (s + 2 == ns && a.ob) {
+                        a.ob[g] = ey[s];
+                        a.ob[a.plane + g] = ex[s];
+                    }
+                }
+            }
+            ryup[s] = ry[s];
+            ryp[s] = ry[s];
+            rxp[s] = rx[s];
+            zp[s] = z;
+        }
+        // histories
+#pragma unroll
+        for (int s = 0; s < TS; ++s) {
+            Ey[s][2] = Ey[s][1];
+            Ex[s][2] = Ex[s][1];
+            Ey[s][1] = Ey[s][0];
+            Ex[s][1] = Ex[s][0];
+        }
+        Ey[0][0] = ly;
+        Ex[0][0] = lx;
+#pragma unroll
+        for (int s = 1; s < TS; ++s) {
+            Ey[s][0] = ey[s - 1];
+            Ex[s][0] = ex[s - 1];
+        }
+        qby1 = lby;
+        qbx1 = lbx;
+#pragma unroll
+        for (int d = NV - 1; d > 0; --d) V[d] = V[d - 1];
+        V[0] = lv;
+    }
+}
+
 template <typename T, int BW, int BH, int TS>
 __global__ __launch_bounds__(256) void fgp_tb_kernel(FgpArgs<T> a) {
     if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
@@ -331,6 +478,14 @@ __global__ __launch_bounds__(256) void fgp_strip_kernel(FgpArgs<T> a) {
     const int gx = div_up(a.W, 256);
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     fgp_strip<T, RC>(a, t / gx, t % gx);
+}
+
+template <typename T, int RC, int TS>
+__global__ __launch_bounds__(256) void fgp_strip_tb_kernel(FgpArgs<T> a) {
+    if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
+    const int gx = div_up(a.W, 256 - 2 * TS);
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    fgp_strip_tb<T, RC, TS>(a, t / gx, t % gx);
 }
 
 // Batched form: block b of the launch works on tile (b - prefix[i]) of slice
@@ -398,19 +553,27 @@ __global__ __launch_bounds__(256) void fgp_strip_batched_kernel(FgpBatchArgs<T> 
     fgp_strip<T, RC>(f, ty, tx);
 }
 
+template <typename T, int RC, int TS>
+__global__ __launch_bounds__(256) void fgp_strip_tb_batched_kernel(FgpBatchArgs<T> a) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int ty, tx;
+    const FgpArgs<T> f = batched_tile<T, 256 - 2 * TS>(a, b, ty, tx);
+    fgp_strip_tb<T, RC, TS>(f, ty, tx);
+}
+
 // ----------------------------------------------------------------- configs
 // Tile shapes compiled in; the autotuner (or the default) picks one by index.
 struct FgpVariant {
     int bw, bh, ts;
-    int strip = 0;  // 1: fgp_strip (bw 256, bh rows per block, ts 1)
+    int strip = 0;  // 1: row-walking strips, bw stored columns (256 - 2 ts), bh rows per block
 };
 static const FgpVariant kFgpVariants[] = {
     {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8},
     {64, 16, 1}, {64, 16, 4}, {64, 32, 4}, {16, 16, 4}, {64, 32, 8},
     // small images (latency-bound: fewer launches per prox call)
     {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2},
-    // one iteration per launch on row-walking strips (HBM-bound sizes)
-    {256, 8, 1, 1}, {256, 32, 1, 1},
+    // row-walking strips (HBM-bound sizes): one iteration per launch, or four
+    {256, 8, 1, 1}, {248, 32, 4, 1}, {248, 64, 4, 1},
 };
 
 template <typename T>
@@ -429,12 +592,20 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
 #undef TVS_FGPV
     const dim3 sgrid(div_up(a.W, 256) * div_up(a.H, V.bh));
 #define TVS_FGPS(RC_)                                                                  \
-    if (V.strip && V.bh == RC_) {                                                      \
+    if (V.strip && V.ts == 1 && V.bh == RC_) {                                         \
         hipLaunchKernelGGL((fgp_strip_kernel<T, RC_>), sgrid, dim3(256), 0, st, a); \
         return;                                                                        \
     }
-    TVS_FGPS(8) TVS_FGPS(32)
+    TVS_FGPS(8)
 #undef TVS_FGPS
+#define TVS_FGPT(RC_, TS_)                                                                   \
+    if (V.strip && V.bh == RC_ && V.ts == TS_) {                                             \
+        const dim3 tgrid(div_up(a.W, 256 - 2 * TS_) * div_up(a.H, RC_));                    \
+        hipLaunchKernelGGL((fgp_strip_tb_kernel<T, RC_, TS_>), tgrid, dim3(256), 0, st, a); \
+        return;                                                                              \
+    }
+    TVS_FGPT(32, 4) TVS_FGPT(64, 4)
+#undef TVS_FGPT
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
 }
 
@@ -529,12 +700,20 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
     if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
 #undef TVS_FGPB
 #define TVS_FGPS(RC_)                                                                            \
-    if (V.strip && V.bh == RC_) {                                                                \
+    if (V.strip && V.ts == 1 && V.bh == RC_) {                                                   \
         hipLaunchKernelGGL((fgp_strip_batched_kernel<T, RC_>), dim3(blocks), dim3(256), 0, st, a); \
         return;                                                                                  \
     }
-    TVS_FGPS(8) TVS_FGPS(32)
+    TVS_FGPS(8)
 #undef TVS_FGPS
+#define TVS_FGPT(RC_, TS_)                                                                   \
+    if (V.strip && V.bh == RC_ && V.ts == TS_) {                                             \
+        hipLaunchKernelGGL((fgp_strip_tb_batched_kernel<T, RC_, TS_>), dim3(blocks), dim3(256), \
+                           0, st, a);                                                        \
+        return;                                                                              \
+    }
+    TVS_FGPT(32, 4) TVS_FGPT(64, 4)
+#undef TVS_FGPT
     throw Error{TVS_ERR_UNSUPPORTED, "FGP tile variant not compiled for this dtype"};
 }
 

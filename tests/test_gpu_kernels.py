@@ -80,6 +80,9 @@ def test_fgp_f32(ctx, H, W):
     assert rel_l2(host(q), q_ref) < 1e-4
 
 
+F32_ONLY = {(64, 32, 8)}  # variants compiled for float32 only
+
+
 def test_fgp_tile_variants_agree_bitwise(ctx):
     """Every compiled tile / temporal-depth variant does the same arithmetic per
     pixel, so all give bit-identical results (a halo or barrier mistake in
@@ -91,7 +94,7 @@ def test_fgp_tile_variants_agree_bitwise(ctx):
         outs = []
         for vi in range(T.tvs_fgp_variant_count()):
             tw, th, ts = T.tvs_fgp_variant(vi)
-            if dt == F64 and (tw, th, ts) == (64, 32, 8):
+            if dt == F64 and (tw, th, ts) in F32_ONLY:
                 continue
             T.tvs_fgp_set_variant(ctx, T.TVS_F64 if dt == F64 else T.TVS_F32, H, W, vi)
             q = torch.zeros(2, H, W, dtype=dt, device="cuda")
@@ -112,19 +115,22 @@ def variant_index(shape):
 
 @pytest.mark.parametrize("H,W", [(37, 600), (9, 513), (70, 256), (17, 257)])
 def test_fgp_strip_variants_span_strips(ctx, H, W):
-    """The row-walking strip variants (256 columns per workgroup) across
-    several strips: the halo columns between strips, a ragged last strip and
-    a ragged last row block give the tile variants' results bit for bit, in
-    both precisions, with and without the nonnegativity constraint."""
+    """The row-walking strip variants (256 columns per workgroup; with TS
+    iterations per launch the strips overlap by TS columns on each side)
+    across several strips: the halo columns between strips, a ragged last
+    strip and row block, and a last launch with fewer than TS iterations
+    (9 iterations) give the tile variants' results bit for bit, in both
+    precisions, with and without the nonnegativity constraint."""
     v = rng(11).standard_normal((H, W))
-    strips = [vi for vi in range(T.tvs_fgp_variant_count()) if T.tvs_fgp_variant(vi)[0] == 256]
-    assert strips
+    strips = [vi for vi in range(T.tvs_fgp_variant_count()) if T.tvs_fgp_variant(vi)[0] >= 240]
+    assert len(strips) >= 2
     ref = variant_index((32, 32, 1))
     for dt in (F64, F32):
         kind = T.TVS_F64 if dt == F64 else T.TVS_F32
         for nonneg in (0, 1):
             outs = []
-            for vi in [ref] + strips:
+            for vi in [ref] + [vi for vi in strips
+                               if not (dt == F64 and T.tvs_fgp_variant(vi) in F32_ONLY)]:
                 T.tvs_fgp_set_variant(ctx, kind, H, W, vi)
                 q = torch.zeros(2, H, W, dtype=dt, device="cuda")
                 z = torch.empty(H, W, dtype=dt, device="cuda")
