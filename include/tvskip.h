@@ -148,7 +148,9 @@ tvs_status tvs_objective(tvs_op* op, tvs_dtype dtype, const void* b, const void*
 /* ------------------------------------------------------------- FGP tuning
  * The FGP kernel is compiled for several output tiles (tile_w x tile_h) and
  * temporal depths (steps: FGP iterations fused per launch, with a halo of
- * `steps` pixels), each with 256 threads.  The context keeps a tuning table:
+ * `steps` pixels), each with 256 threads; the variants with tile_w >= 240
+ * are row-walking strips for large images (a workgroup walks 256 columns,
+ * storing tile_w of them, down tile_h rows).  The context keeps a tuning table:
  * entries per exact size (H, W, dtype), per size class (H and W each
  * rounded up to a power of two, at least 16; written by the autotuner next
  * to the exact entry) and per batched slice count.  An H x W prox uses the

@@ -20,6 +20,12 @@
 // two dual fields, instead of TS times that.  Pixels outside the image are
 // zero and never feed an in-image pixel: every neighbour access is guarded by
 // the image-global boundary conditions.
+//
+// For images far beyond the caches the strip kernels (fgp_strip: one
+// iteration per launch; fgp_strip_tb: TS per launch) instead give each
+// workgroup a 256-column strip that it walks down row by row, so loads and
+// stores are whole aligned row segments, rows are read once, and
+// neighbours come through two LDS rows with one barrier per row.
 #include "tvs_internal.hpp"
 
 namespace tvs {
