@@ -25,11 +25,16 @@ namespace cnn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    // round to nearest even; inputs are finite
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// float -> bf16, round to nearest even: the gfx950 conversion instruction
+// (v_cvt_pk_bf16_f32), which for every finite input gives the integer
+// rounding of the bit pattern (u + 0x7FFF + lsb) >> 16 (checked
+// exhaustively on the device).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// two conversions in one instruction: a in the low half, b in the high half
+__device__ __forceinline__ uint32_t f2bf_pk(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ bool bf_pos(uint16_t b) { return b != 0 && !(b & 0x8000u); }
@@ -67,8 +72,12 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
     // block's lifetime (9 taps x MB x NS x 16 bytes); only the activations
     // go through LDS.  CIN = 2: one K slice, staged once through LDS.
     constexpr int WS = (CIN == 32) ? 8 : COUTP * WST;
+    // CIN = 32: two patch buffers; the next tile's patch is fetched into
+    // registers while the current tile's MFMAs run (one barrier per tile)
+    constexpr int NBUF = (CIN == 32) ? 2 : 1;
+    constexpr int NLD = (P * P * 4 + NT - 1) / NT;  // 16-byte patch loads per thread and part
     __shared__ __attribute__((aligned(16))) uint16_t s_w[NS][WS];
-    __shared__ __attribute__((aligned(16))) uint16_t s_x[NS][P * P * PST];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[NBUF][NS][P * P * PST];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -103,25 +112,50 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                 wreg[sp][0][m] = as_bf8(*(const uint4*)&s_w[sp][(m * 16 + nl) * WST + g * 8]);
     }
 
-    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    // CIN = 32: the input patch of a tile (18 x 18 pixels x 32 channels, zero
+    // outside the image) as NLD 16-byte loads per thread and part
+    uint4 pre[NS][NLD];
+    auto fetch = [&](int tile) {
         const int img = tile / (a.tiles_x * a.tiles_y);
         const int rem = tile % (a.tiles_x * a.tiles_y);
         const int i0 = (rem / a.tiles_x) * CONV_TILE, j0 = (rem % a.tiles_x) * CONV_TILE;
-        __syncthreads();
-        if (CIN == 32) {
 #pragma unroll
-            for (int sp = 0; sp < NS; ++sp) {
-                const uint16_t* src = sp == 0 ? a.in : a.in_lo;
-                for (int idx = tid; idx < P * P * 4; idx += NT) {
-                    int p = idx >> 2, c = idx & 3;
-                    int gi = i0 + p / P - 1, gj = j0 + p % P - 1;
-                    uint4 val = make_uint4(0, 0, 0, 0);
-                    if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-                        val = *(const uint4*)&src[(((size_t)img * H + gi) * W + gj) * 32 + c * 8];
-                    *(uint4*)&s_x[sp][p * PST + c * 8] = val;
-                }
+        for (int sp = 0; sp < NS; ++sp) {
+            const uint16_t* src = sp == 0 ? a.in : a.in_lo;
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const int idx = tid + u * NT;
+                const int p = idx >> 2, c = idx & 3;
+                const int gi = i0 + p / P - 1, gj = j0 + p % P - 1;
+                uint4 val = make_uint4(0, 0, 0, 0);
+                if (idx < P * P * 4 && gi >= 0 && gi < H && gj >= 0 && gj < W)
+                    val = *(const uint4*)&src[(((size_t)img * H + gi) * W + gj) * 32 + c * 8];
+                pre[sp][u] = val;
             }
+        }
+    };
+    if constexpr (CIN == 32) {
+        if ((int)blockIdx.x < a.n_tiles) fetch((int)blockIdx.x);
+    }
+    int buf = 0;
+    for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x, buf ^= (NBUF - 1)) {
+        const int img = tile / (a.tiles_x * a.tiles_y);
+        const int rem = tile % (a.tiles_x * a.tiles_y);
+        const int i0 = (rem / a.tiles_x) * CONV_TILE, j0 = (rem % a.tiles_x) * CONV_TILE;
+        if constexpr (CIN == 32) {
+            // buffer buf was last read two tiles ago, before the previous barrier
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+                for (int u = 0; u < NLD; ++u) {
+                    const int idx = tid + u * NT;
+                    if (idx < P * P * 4)
+                        *(uint4*)&s_x[buf][sp][(idx >> 2) * PST + (idx & 3) * 8] = pre[sp][u];
+                }
+            __syncthreads();
+            if (tile + (int)gridDim.x < a.n_tiles) fetch(tile + (int)gridDim.x);
         } else {
+            __syncthreads();
             for (int p = tid; p < P * P; p += NT) {
                 int gi = i0 + p / P - 1, gj = j0 + p % P - 1;
                 uint32_t hi = 0, lo = 0;
@@ -136,11 +170,11 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                         hi = *(const uint32_t*)&a.in[o * 2];
                     }
                 }
-                *(uint32_t*)&s_x[0][p * PST] = hi;
-                if (SPLIT) *(uint32_t*)&s_x[NS - 1][p * PST] = lo;
+                *(uint32_t*)&s_x[0][0][p * PST] = hi;
+                if (SPLIT) *(uint32_t*)&s_x[0][NS - 1][p * PST] = lo;
             }
+            __syncthreads();
         }
-        __syncthreads();
 
         f32x4 acc[MB][RPW];
 #pragma unroll
@@ -158,7 +192,7 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                     bf16x8 xb[NS];
 #pragma unroll
                     for (int sp = 0; sp < NS; ++sp)
-                        xb[sp] = as_bf8(*(const uint4*)&s_x[sp][(pr * P + pc) * PST + g * 8]);
+                        xb[sp] = as_bf8(*(const uint4*)&s_x[buf][sp][(pr * P + pc) * PST + g * 8]);
 #pragma unroll
                     for (int m = 0; m < MB; ++m) {
                         acc[m][rb] = mfma(wreg[0][t][m], xb[0], acc[m][rb]);
@@ -181,7 +215,7 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
                     for (int j = 0; j < 4; ++j) {
                         const int t = 4 * g + j;
                         const int pr = wave * RPW + rb + t / 3, pc = nl + t % 3;
-                        w4[j] = (t < 9) ? *(const uint32_t*)&s_x[sp][(pr * P + pc) * PST] : 0u;
+                        w4[j] = (t < 9) ? *(const uint32_t*)&s_x[0][sp][(pr * P + pc) * PST] : 0u;
                     }
                     xb[sp] = as_bf8(make_uint4(w4[0], w4[1], w4[2], w4[3]));
                 }
@@ -219,28 +253,31 @@ __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) 
 #pragma unroll
                 for (int m = 0; m < MB; ++m) {
                     const int c0 = m * 16 + 4 * g;
-                    uint16_t o[4], ol[4] = {0, 0, 0, 0};
                     if (OUT == OUT_RELU_BF16) {
+                        float val[4];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const float val = fmaxf(acc[m][rb][r] + a.bias[c0 + r], 0.f);
-                            o[r] = f2bf(val);
-                            if (SPLIT) ol[r] = f2bf(val - bf2f(o[r]));
+                        for (int r = 0; r < 4; ++r) val[r] = fmaxf(acc[m][rb][r] + a.bias[c0 + r], 0.f);
+                        const uint32_t h01 = f2bf_pk(val[0], val[1]), h23 = f2bf_pk(val[2], val[3]);
+                        *(uint2*)&a.out_bf[pix * 32 + c0] = make_uint2(h01, h23);
+                        if (SPLIT) {
+                            // lo = bf16(val - hi)
+                            const uint32_t l01 = f2bf_pk(val[0] - __uint_as_float(h01 << 16),
+                                                         val[1] - __uint_as_float(h01 & 0xFFFF0000u));
+                            const uint32_t l23 = f2bf_pk(val[2] - __uint_as_float(h23 << 16),
+                                                         val[3] - __uint_as_float(h23 & 0xFFFF0000u));
+                            *(uint2*)&a.out_lo[pix * 32 + c0] = make_uint2(l01, l23);
                         }
                     } else {  // OUT_MASK_BF16
                         uint2 mk = *(const uint2*)&a.mask[pix * 32 + c0];
                         uint16_t mm[4] = {(uint16_t)(mk.x & 0xFFFF), (uint16_t)(mk.x >> 16),
                                           (uint16_t)(mk.y & 0xFFFF), (uint16_t)(mk.y >> 16)};
+                        uint16_t o[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) o[r] = bf_pos(mm[r]) ? f2bf(acc[m][rb][r]) : (uint16_t)0;
+                        *(uint2*)&a.out_bf[pix * 32 + c0] =
+                            make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                                       (uint32_t)o[2] | ((uint32_t)o[3] << 16));
                     }
-                    *(uint2*)&a.out_bf[pix * 32 + c0] =
-                        make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
-                                   (uint32_t)o[2] | ((uint32_t)o[3] << 16));
-                    if (SPLIT && OUT == OUT_RELU_BF16)
-                        *(uint2*)&a.out_lo[pix * 32 + c0] =
-                            make_uint2((uint32_t)ol[0] | ((uint32_t)ol[1] << 16),
-                                       (uint32_t)ol[2] | ((uint32_t)ol[3] << 16));
                 }
             }
         }
