@@ -604,9 +604,12 @@ void launch_conv(tvs_ctx* ctx, int cin, int coutp, int in_mode, int out_mode, bo
     TVS_REQUIRE(!split || out_mode != OUT_MASK_BF16, TVS_ERR_UNSUPPORTED,
                 "conv3x3: the input-gradient pass is single-part");
     hipStream_t st = ctx->stream;
-    // register-resident weights leave room for two 4-wave blocks (single
-    // part) or one 8-wave block (two parts) per CU
-    const dim3 grid(grid_for(ctx, a.n_tiles, split ? 1 : 2)), block(split ? 512 : 256);
+    // register-resident weights (32 input channels) leave room for two 4-wave
+    // blocks (single part) or one 8-wave block (two parts) per CU, three for
+    // the 2-channel output layer; the first layer (2 input channels, weights
+    // through LDS) fits four single-part blocks or two two-part blocks
+    const int per_cu = cin == 2 ? (split ? 2 : 4) : (coutp == 16 && !split ? 3 : (split ? 1 : 2));
+    const dim3 grid(grid_for(ctx, a.n_tiles, per_cu)), block(split ? 512 : 256);
 #define TVS_CONV(CI, CO, IM, OM, SP) conv3x3_kernel<CI, CO, IM, OM, SP><<<grid, block, 0, st>>>(a)
     if (cin == 2 && coutp == 32 && in_mode == IN_VLAM && out_mode == OUT_RELU_BF16) {
         if (split) TVS_CONV(2, 32, IN_VLAM, OUT_RELU_BF16, true);
