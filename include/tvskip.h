@@ -407,7 +407,8 @@ tvs_status tvs_cnn_train_step(tvs_cnn* cnn, int n, int H, int W, const float* v,
  * gap(q) / P(z_q) (the gap of eq. (6) in the form gap(q) = sum_i lam
  * |(D z_q)_i| - <(D z_q)_i, q_i>, P the prox objective) exceeds gap_tol
  * (or is NaN) and fallback_iters > 0, FGP runs fallback_iters iterations
- * warm-started from q and q_out gets its final dual.  z_out gets
+ * warm-started from q (from zero when the gap is not finite) and q_out gets
+ * its final dual.  z_out gets
  * P_X(v + div q_out).  fell_back_out (nullable) is set to 1 when FGP ran;
  * rel_gap_out (nullable) gets the network's relative gap.  Synchronises
  * (the gate is decided on the host). */

@@ -510,6 +510,9 @@ extern "C" tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, d
         gap_host<float>(cnn->ctx, H, W, v, lam, nn, q_out, &g, &pr);
         const double rel = pr > 0 ? g / pr : g;
         const bool fb = !(rel <= gap_tol) && fallback_iters > 0;  // a NaN gap falls back
+        // ... from the zero dual when the gap is not finite: such a network
+        // dual (overflowed activations) is no warm start
+        if (fb && !std::isfinite(rel)) launch_fill<float>(cnn->ctx, (size_t)2 * H * W, 0.0f, q_out);
         tv_prox_impl<float>(cnn->ctx, H, W, v, lam, fb ? fallback_iters : 0, nn, q_out, z_out,
                             nullptr);
         if (fell_back_out) *fell_back_out = fb ? 1 : 0;

@@ -135,6 +135,42 @@ def test_zero_network_gate_closed_starts_from_better_dual(ctx, zero_cnn):
         T.tvs_op_destroy(op)
 
 
+def test_nan_network_always_falls_back(ctx):
+    """A network whose float32 activations overflow (all parameters 1e30, as
+    after diverged training) yields NaN duals (inf scaled by 0 in the ball
+    projection) and a NaN gap: every call falls back, inside a solver run
+    from the previous call's dual, so the run equals the plain run bit for
+    bit (graph and stream), and the standalone prox runs FGP from the zero
+    dual."""
+    cnn = T.tvs_cnn_create(ctx, 1)
+    T.tvs_cnn_set_params(cnn, np.full(T.tvs_cnn_param_count(), 1e30, dtype=np.float32))
+    A, b, L, op = ct_setup(ctx)
+    N, (na, nd) = A.H, A.out_shape
+    K, Kin, p, seed = 40, 10, 0.3, 12
+    try:
+        ref = [zeros((N, N)), zeros((N, N)), zeros((2, N, N)), zeros((na, nd))]
+        r0 = T.tvs_pdhgskip(op, dev(b, F32), *ref, 0.05, 1 / L, 1 / L, p, K, Kin, nonneg=1,
+                            seed=seed)
+        for graph in (False, True):
+            st = [zeros((N, N)), zeros((N, N)), zeros((2, N, N)), zeros((na, nd))]
+            r = T.tvs_pdhgskip_ex(op, dev(b, F32), *st, 0.05, 1 / L, 1 / L, p, K, Kin, nonneg=1,
+                                  seed=seed, graph=graph, cnn=cnn, gap_tol=1.0)
+            assert r["n_fallback"] == r["n_prox"] == r0["n_prox"] > 0
+            for k in range(4):
+                assert torch.equal(st[k], ref[k]), (graph, k)
+        v = dev(A.adjoint(b) / N, F32)  # some image
+        q = torch.empty(2, N, N, dtype=F32, device="cuda")
+        z = torch.empty(N, N, dtype=F32, device="cuda")
+        fb, rg = T.tvs_cnn_prox(cnn, v, 0.2, 1, 1.0, 15, q, z)
+        assert fb and not np.isfinite(rg)
+        q0, z0 = zeros((2, N, N)), torch.empty(N, N, dtype=F32, device="cuda")
+        T.tvs_tv_prox(ctx, v, 0.2, 15, 1, q0, z0)
+        assert torch.equal(q, q0) and torch.equal(z, z0)
+    finally:
+        T.tvs_op_destroy(op)
+        T.tvs_cnn_destroy(cnn)
+
+
 def test_learned_solver_rejects_float64(ctx, zero_cnn):
     N = 16
     _, b = denoise_problem(N, dtype=torch.float64)
