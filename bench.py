@@ -147,7 +147,7 @@ def main():
     # ---- batched form: 256 uneven denoising slices in one graph vs one solve per slice
     batched = None
     if not args.no_batched:
-        batched = batched_bench(T, ctx)
+        batched = batched_bench(T)
 
     # ---- light-prox problems (Dual-ROF / Dual-Huber-ROF, 200 x 300)
     light = None
@@ -644,13 +644,15 @@ def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
     return res
 
 
-def batched_bench(T, ctx, K=500, Kin=50):
+def batched_bench(T, K=500, Kin=50):
     """The batched workload (256 slices, sizes 128..1024 squared, per-slice
     alpha and p, A = I, gamma = 1, 500 outer iterations, 50 FGP iterations):
     one batched run captured in a HIP graph, against the plain method, one
     single-image solve per slice.  Both produce identical iterates (tested),
     so any time-to-accuracy target is reached at the same iteration counts
-    and the ratio of run times is the ratio of times to that accuracy."""
+    and the ratio of run times is the ratio of times to that accuracy.  Both
+    sides run on FGP variants picked by the autotuner, in a context of their
+    own: the batched run's for the batch, the plain run's per slice size."""
     import numpy as np
     import torch
     import synth
@@ -670,6 +672,12 @@ def batched_bench(T, ctx, K=500, Kin=50):
     x = torch.zeros(total, device=dev)
     h = torch.zeros_like(x)
     q = torch.zeros(2 * total, device=dev)
+    ctx = T.tvs_ctx_create(0)  # its own tuning table
+    tuned = {}
+    for n in sorted({s["H"] for s in sp}):
+        vi, _ = T.tvs_fgp_autotune(ctx, T.TVS_F32, n, n, Kin, 2)
+        tuned[str(n)] = list(T.tvs_fgp_variant(vi))
+    vb, _ = T.tvs_fgp_autotune_batched(ctx, T.TVS_F32, slices, Kin, 2)
 
     def run_batched():
         for t in (x, h, q):
@@ -721,9 +729,11 @@ def batched_bench(T, ctx, K=500, Kin=50):
            "prox_calls": int(np.sum(nprox)),
            "batched_ms": round(ms_b, 2), "plain_per_slice_ms": round(ms_p, 2),
            "speedup": round(ms_p / ms_b, 3),
-           "batched_Gpx_iters_per_s": round(px * K / (ms_b * 1e-3) / 1e9, 3)}
+           "batched_Gpx_iters_per_s": round(px * K / (ms_b * 1e-3) / 1e9, 3),
+           "fgp_variant_batched": list(T.tvs_fgp_variant(vb)), "fgp_variant_per_size": tuned}
     log(f"batched: {res}")
     del x, h, q, b
+    T.tvs_ctx_destroy(ctx)
     torch.cuda.empty_cache()
     return res
 
