@@ -827,9 +827,29 @@ def cpu_baseline(b, w, ang, sigma, tau, seed, target_s=12.0):
     r = O.pdhgskip(A, b, w.alpha, sigma, tau, w.p, n, w.inner_iters, nonneg=1, seed=seed)
     el = time.perf_counter() - t0
     log(f"CPU oracle: {n} iterations in {el:.2f} s on {threads} threads ({r['nprox']} prox)")
-    return {"value": round(n / el, 4), "unit": "outer_iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the {w.outer_iters} outer iterations of the same run "
-                      f"({r['nprox']} prox calls, float64)", "seconds": round(el, 2)}
+    out = {"value": round(n / el, 4), "unit": "outer_iters/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} of the {w.outer_iters} outer iterations of the same run "
+                     f"({r['nprox']} prox calls, float64)", "seconds": round(el, 2)}
+    # the same on one thread (OpenMP runtime of the oracle library), shorter sample
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        gomp = None
+    if gomp is not None and threads > 1:
+        gomp.omp_set_num_threads(1)
+        try:
+            n1 = max(2, min(40, int(4.0 / max(per * threads, 1e-3))))
+            t0 = time.perf_counter()
+            r1 = O.pdhgskip(A, b, w.alpha, sigma, tau, w.p, n1, w.inner_iters, nonneg=1, seed=seed)
+            el1 = time.perf_counter() - t0
+        finally:
+            gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": round(n1 / el1, 4),
+                                "sample": f"first {n1} outer iterations ({r1['nprox']} prox calls)",
+                                "seconds": round(el1, 2)}
+        log(f"CPU oracle, one thread: {n1} iterations in {el1:.2f} s")
+    return out
 
 
 if __name__ == "__main__":
