@@ -141,6 +141,44 @@ def test_fgp_strip_variants_span_strips(ctx, H, W):
                 assert np.array_equal(z, outs[0][0]) and np.array_equal(q, outs[0][1]), (dt, nonneg)
 
 
+def test_fgp_8192_strips_bitwise_and_sampled_windows(ctx):
+    """FGP at 8192^2 float32 in the launch configurations the benchmark times
+    (row-walking strips, one and four iterations per launch) gives the tile
+    kernel's bits, and sampled windows agree with the oracle: after K
+    iterations an output pixel depends only on inputs within distance K, so
+    the oracle run on a window with a margin of K + 1 pixels (its own
+    boundary conditions at the window edge) is exact in the window's middle."""
+    n, K, lam = 8192, 6, 0.05
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.rand(n, n, device="cuda", generator=g)
+    outs = {}
+    for shape in [(64, 16, 1), (256, 8, 1), (248, 32, 4), (248, 64, 4)]:
+        T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, variant_index(shape))
+        q = torch.zeros(2, n, n, device="cuda")
+        z = torch.empty(n, n, device="cuda")
+        T.tvs_tv_prox(ctx, v, lam, K, 0, q, z)
+        outs[shape] = (q, z)
+    T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, -1)
+    q0, z0 = outs[(64, 16, 1)]
+    for shape, (q, z) in outs.items():
+        assert torch.equal(q, q0) and torch.equal(z, z0), shape
+    del outs
+    m = K + 2
+    # corners, strip and row-block seams (248, 256, 496 columns; 8, 32, 64 rows), interior
+    for (i, j) in [(0, 0), (0, n - 24), (n - 24, 0), (n - 24, n - 24), (56, 240), (28, 490),
+                   (4100, 4090), (60, 248)]:
+        i0, j0 = max(i - m, 0), max(j - m, 0)
+        i1, j1 = min(i + 24 + m, n), min(j + 24 + m, n)
+        vw = host(v[i0:i1, j0:j1]).astype(np.float64)
+        zo, qo = O.fgp(vw, lam, K, 0)
+        ci0, cj0 = i - i0, j - j0
+        sl = (slice(ci0, ci0 + 24), slice(cj0, cj0 + 24))
+        zg = host(z0[i:i + 24, j:j + 24])
+        qg = host(q0[:, i:i + 24, j:j + 24])
+        assert np.abs(zg - zo[sl]).max() <= 1e-5 * max(1.0, np.abs(zo[sl]).max()), (i, j)
+        assert np.abs(qg - qo[(slice(None),) + sl]).max() <= 1e-5, (i, j)
+
+
 def test_tv_prox_identity_cases_bitwise(ctx):
     H, W = 70, 90
     v = rng(9).standard_normal((H, W))
