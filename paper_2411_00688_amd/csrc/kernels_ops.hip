@@ -832,11 +832,16 @@ __device__ __forceinline__ long long wave_uniform64(long long v) {
 // 63: the permute takes the lane modulo 64).  h is clamped into [-1, RD_P + 1]
 // first: a ray outside the strip then pushes to lanes 62 and 63 or RD_P and
 // RD_P + 1, none of which is a pixel of the strip, so no range test is needed.
-__device__ __forceinline__ void rd_dest(long long U, int& da, int& db) {
+// Returns the address for lane h - 1; lane h's is that + 4, which the
+// permute instruction takes as its immediate offset.
+__device__ __forceinline__ int rd_dest(long long U) {
     int h = (int)(U >> 32);
     h = h < -1 ? -1 : (h > RD_P + 1 ? RD_P + 1 : h);
-    db = 4 * h;
-    da = db - 4;
+    int da = 4 * h - 4;
+    // opaque to the optimiser (no instruction), which would otherwise fold
+    // da + 4 back into 4 h and compute both addresses
+    __asm__("" : "+v"(da));
+    return da;
 }
 
 // The steps of one angle for one wavefront.  U: the lane's ray position
@@ -857,11 +862,10 @@ __device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long lo
             // (1 - f = fl(1 - fr 2^-32), f val = fl(fr (val 2^-32)), fr the
             // float fraction word: the same roundings in fewer operations)
             const float fr = (float)(unsigned)U;
-            int da, db;
-            rd_dest(U, da, db);
+            const int da = rd_dest(U);
             const float wa = fmaf(fr, -2.3283064365386963e-10f, 1.0f) * val, wb = fr * vs;
             const float ra = __int_as_float(__builtin_amdgcn_ds_permute(da, __float_as_int(wa)));
-            const float rb = __int_as_float(__builtin_amdgcn_ds_permute(db, __float_as_int(wb)));
+            const float rb = __int_as_float(__builtin_amdgcn_ds_permute(da + 4, __float_as_int(wb)));
             acc[k] += ra + rb;
             U += dU;
         }
