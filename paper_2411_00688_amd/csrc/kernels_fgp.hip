@@ -576,8 +576,9 @@ struct FgpVariant {
 static const FgpVariant kFgpVariants[] = {
     {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8},
     {64, 16, 1}, {64, 16, 4}, {64, 32, 4}, {16, 16, 4}, {64, 32, 8},
-    // small images (latency-bound: fewer launches per prox call)
-    {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2},
+    // small images (latency-bound: fewer launches per prox call; a depth
+    // that divides the iteration count saves a short last launch)
+    {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2}, {16, 16, 5},
     // row-walking strips (HBM-bound sizes): one iteration per launch, or four
     {256, 8, 1, 1}, {248, 32, 4, 1}, {248, 64, 4, 1},
 };
@@ -594,6 +595,7 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     TVS_FGPV(32, 32, 1) TVS_FGPV(32, 32, 2) TVS_FGPV(32, 32, 4) TVS_FGPV(32, 32, 8)
     TVS_FGPV(64, 16, 1) TVS_FGPV(64, 16, 4) TVS_FGPV(64, 32, 4) TVS_FGPV(16, 16, 4)
     TVS_FGPV(16, 16, 8) TVS_FGPV(32, 16, 4) TVS_FGPV(32, 16, 8) TVS_FGPV(16, 16, 2)
+    TVS_FGPV(16, 16, 5)
     if (sizeof(T) == 4) { TVS_FGPV(64, 32, 8) }
 #undef TVS_FGPV
     const dim3 sgrid(div_up(a.W, 256) * div_up(a.H, V.bh));
@@ -703,6 +705,7 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
     TVS_FGPB(32, 32, 1) TVS_FGPB(32, 32, 2) TVS_FGPB(32, 32, 4) TVS_FGPB(32, 32, 8)
     TVS_FGPB(64, 16, 1) TVS_FGPB(64, 16, 4) TVS_FGPB(64, 32, 4) TVS_FGPB(16, 16, 4)
     TVS_FGPB(16, 16, 8) TVS_FGPB(32, 16, 4) TVS_FGPB(32, 16, 8) TVS_FGPB(16, 16, 2)
+    TVS_FGPB(16, 16, 5)
     if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
 #undef TVS_FGPB
 #define TVS_FGPS(RC_)                                                                            \
