@@ -428,7 +428,7 @@ def fgp_hbm(T, ctx, n, Kin):
     q = torch.zeros(2, n, n, device=dev)
     z = torch.empty(n, n, device=dev)
     res = {"size": n}
-    iters = 10
+    iters = 40  # a multiple of every depth in the variant table: every launch is a full one
 
     def rate(vi):
         T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, vi)
