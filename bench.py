@@ -59,7 +59,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE "
-              f"{world}); this build has no multi-GPU path.", flush=True)
+              f"{world}); the library has no multi-GPU path.", flush=True)
         sys.exit(2)
 
     import numpy as np

@@ -294,8 +294,8 @@ tvs_status tvs_dual_rof_proxskip(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, co
                                  uint8_t* theta_trace, int64_t* n_prox_out);
 
 /* ---------------------------------------------------------- batched form
- * Many independent ProxSkip TV-denoising problems (A = I, Sec. 2; the
- * batched workload of the build) of uneven sizes, solved together: each
+ * Many independent ProxSkip TV-denoising problems (A = I, Sec. 2; e.g. the
+ * slices of a volume or a stack of images) of uneven sizes, solved together: each
  * outer iteration is one data-step launch over every slice, FGP launches over
  * the slices whose coin came up (work lists built on the host from the
  * counter-based coin), and one finalize launch; with TVS_FLAG_GRAPH the whole

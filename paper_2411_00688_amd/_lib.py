@@ -143,8 +143,8 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
-                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
-                f"g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+                f"{LIB_PATH} is missing: build it with `python -m paper_2411_00688_amd.build` "
+                f"(hipcc, gfx950). There is no CPU fallback.")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in PROTOTYPES.items():
             f = getattr(L, name)
