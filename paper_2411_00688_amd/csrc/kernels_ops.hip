@@ -770,6 +770,9 @@ static constexpr int RD_P = 52;     // tile side
 static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 24;  // at most this many angles per group
+static constexpr int RD_H = 2;      // wavefront sets per tile, set h taking angles h, h + 2, ...
+static constexpr int RD_T = 64 * 4 * RD_H;  // threads per block
+static_assert(RD_H == 2, "the two sets' sums are combined in pairs");
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
 static_assert(RD_P + 1 < 62, "the lanes past the strip (RD_P, RD_P + 1, 62, 63) are no pixel lanes");
 
@@ -876,10 +879,10 @@ __device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long lo
 template <int CLS>
 __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float (*yS)[RD_NB],
                                          const int* wst, const int* ecls, const int (*eD)[4],
-                                         const long long (*eK)[4], int g, int G,
-                                         int na_g, int w, int lane, int n_s, float (&acc)[RD_L]) {
+                                         const long long (*eK)[4], int g, int G, int na_g,
+                                         int hf, int w, int lane, int n_s, float (&acc)[RD_L]) {
     if (n_s <= 0) return;
-    for (int m = 0; m < na_g; ++m) {
+    for (int m = hf; m < na_g; m += RD_H) {
         if (ecls[m] != CLS) continue;
         const JAngle& gg = a.ang[g + m * G];
         const int d0 = __builtin_amdgcn_readfirstlane(eD[m][w]);
@@ -896,7 +899,7 @@ __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float
     }
 }
 
-__global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
+__global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
     __shared__ float yS[RD_MAXA][RD_NB];
     __shared__ int wst[RD_MAXA];
     __shared__ int ecls[RD_MAXA];
@@ -904,6 +907,7 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     __shared__ int eD[RD_MAXA][4];
     __shared__ long long eK[RD_MAXA][4];
     __shared__ float tileT[RD_P][RD_P + 1];
+    __shared__ float rowS[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
     const int tiles_x = div_up(a.W, RD_P), tiles = tiles_x * div_up(a.H, RD_P);
@@ -911,7 +915,9 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     const int G = a.groups, g = L / tiles, tl = L - (L / tiles) * tiles;
     const int i0 = (tl / tiles_x) * RD_P, j0 = (tl % tiles_x) * RD_P;
     const int tid = (int)threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // wavefront -> (angle set hf, band of RD_L rows / columns w)
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w = wv & 3, hf = wv >> 2;
     const int na_g = (a.n_ang - g + G - 1) / G;
     if (tid < na_g) {
         const JAngle& gg = a.ang[g + tid * G];
@@ -924,21 +930,21 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
         rd_entry(a.ang[g + m * G], i0, j0, ww, eD[m][ww], eK[m][ww]);
     }
     __syncthreads();
-    // the group's sinogram windows, RD_MAXA * RD_NB / 256 loads per thread
+    // the group's sinogram windows, RD_MAXA * RD_NB / RD_T loads per thread
     // issued together (a loop over the runtime count would wait for each)
     {
-        constexpr int NL = (RD_MAXA * RD_NB + 255) / 256;
+        constexpr int NL = (RD_MAXA * RD_NB + RD_T - 1) / RD_T;
         float v[NL];
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
-            const int idx = tid + 256 * r;
+            const int idx = tid + RD_T * r;
             const int m = idx / RD_NB, bb = idx - m * RD_NB;
             const int d = m < na_g ? wst[m] + bb : -1;
             v[r] = (d >= 0 && d < a.n_det) ? a.y[(size_t)(g + m * G) * a.n_det + d] : 0.0f;
         }
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
-            const int idx = tid + 256 * r;
+            const int idx = tid + RD_T * r;
             const int m = idx / RD_NB, bb = idx - m * RD_NB;
             if (m < na_g) yS[m][bb] = wgtS[m] * v[r];
         }
@@ -949,20 +955,32 @@ __global__ __launch_bounds__(256) void joseph_adj_rd_kernel(JAdjRdArgs<float> a)
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
     const int nR = __builtin_amdgcn_readfirstlane(a.H - (i0 + RD_L * w));
     const int nC = __builtin_amdgcn_readfirstlane(a.W - (j0 + RD_L * w));
-    rd_class<0>(a, yS, wst, ecls, eD, eK, g, G, na_g, w, lane, nR, accR);
-    rd_class<1>(a, yS, wst, ecls, eD, eK, g, G, na_g, w, lane, nC, accC);
-    // column-stepping sums are held per (column = 13 w + k, row = lane): transpose
-    if (lane < RD_P) {
+    rd_class<0>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
+    rd_class<1>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+    // Column-stepping sums are held per (column = 13 w + k, row = lane) and
+    // are transposed through tileT.  Set 1 stores both its sums, set 0 adds
+    // its column sums in place and writes the tile: a fixed order per pixel.
+    if (hf == 1 && lane < RD_P) {
 #pragma unroll
-        for (int k = 0; k < RD_L; ++k) tileT[lane][RD_L * w + k] = accC[k];
+        for (int k = 0; k < RD_L; ++k) {
+            tileT[lane][RD_L * w + k] = accC[k];
+            rowS[RD_L * w + k][lane] = accR[k];
+        }
     }
     __syncthreads();
+    if (hf == 0 && lane < RD_P) {
+#pragma unroll
+        for (int k = 0; k < RD_L; ++k) tileT[lane][RD_L * w + k] += accC[k];
+    }
+    __syncthreads();
+    if (hf != 0) return;
     const size_t plane = (size_t)a.H * a.W;
 #pragma unroll
     for (int k = 0; k < RD_L; ++k) {
         const int i = i0 + RD_L * w + k, j = j0 + lane;
         if (lane < RD_P && i < a.H && j < a.W)
-            a.part[(size_t)g * plane + (size_t)i * a.W + j] = accR[k] + tileT[RD_L * w + k][lane];
+            a.part[(size_t)g * plane + (size_t)i * a.W + j] =
+                accR[k] + rowS[RD_L * w + k][lane] + tileT[RD_L * w + k][lane];
     }
 }
 
@@ -1058,7 +1076,7 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
             r.W = a.W;
             r.n_det = a.n_det;
             r.part = part;
-            hipLaunchKernelGGL(joseph_adj_rd_kernel, dim3(tiles * G), dim3(256), 0, ctx->stream, r);
+            hipLaunchKernelGGL(joseph_adj_rd_kernel, dim3(tiles * G), dim3(RD_T), 0, ctx->stream, r);
             TVS_LAUNCH_CHECK();
             hipLaunchKernelGGL((joseph_adj_sum_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)),
                                dim3(1024), 0, ctx->stream, (const T*)part, G, a.H, a.W, x_out, a.ps,
