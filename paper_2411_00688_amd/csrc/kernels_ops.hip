@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
 static constexpr int RD_P = 52;     // tile side
 static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
-static constexpr int RD_MAXA = 24;  // at most this many angles per group
+static constexpr int RD_MAXA = 36;  // at most this many angles per group
 static constexpr int RD_H = 2;      // wavefront sets per tile, set h taking angles h, h + 2, ...
 static constexpr int RD_T = 64 * 4 * RD_H;  // threads per block
 static_assert(RD_H == 2, "the two sets' sums are combined in pairs");
