@@ -15,9 +15,15 @@ Parity status of each function (what pins it lives in tests/test_oracle_*.py):
   proxskip / pdhgskip ............. pinned (p = 1 equals the separately written
                                      PGD / PDHG bitwise; fixed points; same
                                      minimiser as the reference solver)
-  coin ............................ pinned (published SplitMix64 output values,
-                                     Bernoulli statistics)
+  coin ............................ pinned (published SplitMix64 outputs of
+                                     state 0, Bernoulli and run statistics)
   op_norm ......................... pinned (identity, blur = 1, SVD of small A)
+  subset, subset_apply/adjoint .... pinned (uniform counts, pure function of
+                                     (seed, stream, k); the rows of the full A)
+  spdhgskip ....................... pinned (untouched subsets keep their rows
+                                     bitwise; z = A^T y after a run; converges
+                                     to the minimiser of PDHG / the explicit
+                                     solver at several n and p)
   pdhg_explicit ................... pinned (agrees with PGD/PDHG minimisers and
                                      with the exact 1-D/2-pixel solutions)
   dual_rof_proxskip ............... pinned (p = 1 equals the separately written
@@ -94,6 +100,13 @@ def lib():
         L.orc_pdhgskip.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, dp, C.POINTER(OrcParams), u8p, dp]
         L.orc_pdhgskip.restype = C.c_int64
         L.orc_pdhg.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, C.POINTER(OrcParams), dp]
+        L.orc_subset.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int]
+        L.orc_subset.restype = C.c_int
+        L.orc_subset_apply.argtypes = [C.POINTER(OrcOp), C.c_int, C.c_int, dp, dp]
+        L.orc_subset_adjoint.argtypes = [C.POINTER(OrcOp), C.c_int, C.c_int, dp, dp]
+        L.orc_spdhgskip.argtypes = [C.POINTER(OrcOp), dp, C.c_int, dp, dp, dp, dp,
+                                    C.POINTER(OrcParams), u8p, C.POINTER(C.c_int32), dp]
+        L.orc_spdhgskip.restype = C.c_int64
         L.orc_op_norm.argtypes = [C.POINTER(OrcOp), C.c_int, C.c_uint64]
         L.orc_op_norm.restype = C.c_double
         L.orc_pdhg_explicit.argtypes = [C.POINTER(OrcOp), dp, C.c_double, C.c_int, C.c_int64,
@@ -303,6 +316,50 @@ def pdhg(A: Op, b, alpha, sigma, tau, outer, inner, nonneg=0, x=None, y=None, q=
     lib().orc_pdhg(C.byref(A.s), _p(b), _p(x), _p(y), _p(q), C.byref(P),
                    _p(obj) if want_obj else None)
     return dict(x=x, y=y, q=q, obj=obj)
+
+
+def subset(seed, stream, k, n) -> int:
+    """Angle subset drawn at outer iteration k (uniform on 0..n-1)."""
+    return int(lib().orc_subset(seed & 0xFFFFFFFFFFFFFFFF, stream & 0xFFFFFFFFFFFFFFFF, int(k),
+                                int(n)))
+
+
+def subset_rows(n_ang, n, j):
+    """Angle indices of subset j of n (the rows of A_j in order)."""
+    return np.arange(j, n_ang, n)
+
+
+def subset_apply(A: Op, n, j, x):
+    x = _f64(x)
+    yj = np.empty((len(subset_rows(A.out_shape[0], n, j)), A.out_shape[1]))
+    lib().orc_subset_apply(C.byref(A.s), int(n), int(j), _p(x), _p(yj))
+    return yj
+
+
+def subset_adjoint(A: Op, n, j, yj):
+    yj = _f64(yj)
+    x = np.empty((A.H, A.W))
+    lib().orc_subset_adjoint(C.byref(A.s), int(n), int(j), _p(yj), _p(x))
+    return x
+
+
+def spdhgskip(A: Op, b, n_sub, alpha, sigma, tau, p, outer, inner, nonneg=0, seed=0, stream=0,
+              k0=0, x=None, h=None, y=None, q=None, want_obj=False):
+    """SPDHG over angle subsets with the skipped prox.  Returns dict(x, h, y,
+    q, theta, subset, obj, nprox)."""
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, h, q = _state(x, (H, W)), _state(h, (H, W)), _state(q, (2, H, W))
+    y = _state(y, A.out_shape)
+    theta = np.zeros(outer, dtype=np.uint8)
+    sub = np.zeros(outer, dtype=np.int32)
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, sigma, tau, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_spdhgskip(C.byref(A.s), _p(b), int(n_sub), _p(x), _p(h), _p(y), _p(q),
+                            C.byref(P), theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                            sub.ctypes.data_as(C.POINTER(C.c_int32)),
+                            _p(obj) if want_obj else None)
+    return dict(x=x, h=h, y=y, q=q, theta=theta, subset=sub, obj=obj, nprox=int(n))
 
 
 def pdhg_explicit(A: Op, b, alpha, nonneg, iters, x=None, y1=None, y2=None, obj_every=0):

@@ -510,6 +510,121 @@ int64_t orc_pdhgskip(const orc_op* A, const double* b, double* x, double* h,
     return nprox;
 }
 
+/* ------------------------------------------------------------------------
+ * Stochastic angle subsets with the prox skip: the paper's "Discussion and
+ * Future work" proposes drawing a random subset of the projection angles
+ * per iteration in addition to the random prox.  The reading: SPDHG
+ * (Chambolle, Ehrhardt, Richtarik and Schoenlieb, SIAM J. Optim. 28(4),
+ * 2018), a published stochastic primal-dual method, with f = sum_j f_j,
+ * f_j(y_j) = 1/2 |y_j - b_j|^2 over the angle subsets j, uniform sampling
+ * (p_j = 1/n) and its dual extrapolation, and the primal prox of g skipped
+ * with a control variate exactly as in Alg. "PDHGSkip-2":
+ *   w = x_k - sigma zbar_k;  xhat = w + sigma h_k
+ *   theta_k = 1: x_{k+1} = prox_{(sigma/p) g}(w + (sigma - sigma/p) h_k),
+ *                h_{k+1} = h_k + (p/sigma)(x_{k+1} - xhat)
+ *   theta_k = 0: x_{k+1} = xhat
+ *   j = j_k:  y_j+ = prox_{tau f_j*}(y_j + tau A_j x_{k+1})
+ *                  = (y_j + tau (A_j x_{k+1} - b_j)) / (1 + tau)
+ *   delta = A_j^T (y_j+ - y_j);  z_{k+1} = z_k + delta;
+ *   zbar_{k+1} = z_{k+1} + n delta   (the extrapolation 1 / p_j)
+ * and z_0 = zbar_0 = A^T y_0.  The subset draw comes from the coin's
+ * counter-based generator on the stream stream_id xor 2^63:
+ *   j_k = floor((r_k >> 11) n / 2^53), exact in 64-bit integers.
+ * ------------------------------------------------------------------------ */
+int orc_subset(uint64_t seed, uint64_t stream_id, int64_t k, int n) {
+    if (n < 1 || k < 0) return -1;
+    uint64_t s2 = stream_id ^ 0x8000000000000000ULL;
+    uint64_t key = orc_splitmix64_mix(seed ^ orc_splitmix64_mix(s2 + ORC_GOLDEN));
+    uint64_t r = orc_splitmix64_mix(key + (uint64_t)(k + 1) * ORC_GOLDEN);
+    return (int)(((r >> 11) * (uint64_t)n) >> 53);
+}
+
+/* The Joseph operator restricted to the angles j, j + n, ... */
+static orc_op subset_op(const orc_op* A, int n, int j, double* ang) {
+    orc_op S = *A;
+    int c = 0;
+    for (int a = j; a < A->n_ang; a += n) ang[c++] = A->angles[a];
+    S.n_ang = c;
+    S.angles = ang;
+    return S;
+}
+
+void orc_subset_apply(const orc_op* A, int n, int j, const double* x, double* yj) {
+    double* ang = dalloc((size_t)A->n_ang);
+    orc_op S = subset_op(A, n, j, ang);
+    orc_op_apply(&S, x, yj);
+    free(ang);
+}
+
+void orc_subset_adjoint(const orc_op* A, int n, int j, const double* yj, double* x) {
+    double* ang = dalloc((size_t)A->n_ang);
+    orc_op S = subset_op(A, n, j, ang);
+    orc_op_adjoint(&S, yj, x);
+    free(ang);
+}
+
+int64_t orc_spdhgskip(const orc_op* A, const double* b, int n_sub, double* x, double* h,
+                      double* y, double* q, const orc_params* P, uint8_t* theta_trace,
+                      int32_t* subset_trace, double* obj_trace) {
+    int H = A->H, W = A->W, nd = A->n_det;
+    size_t n = (size_t)H * W;
+    double sigma = P->step, tau = P->dual_step, p = P->p;
+    double lam = P->alpha * sigma / p;
+    double coef = sigma - sigma / p;
+    double rate = p / sigma;
+    int rows_max = (A->n_ang + n_sub - 1) / n_sub;
+    double* z = dalloc(n);
+    double* zbar = dalloc(n);
+    double* w = dalloc(n);
+    double* xhat = dalloc(n);
+    double* v = dalloc(n);
+    double* xn = dalloc(n);
+    double* delta = dalloc(n);
+    double* kx = dalloc((size_t)rows_max * nd);
+    double* dy = dalloc((size_t)rows_max * nd);
+    orc_op_adjoint(A, y, z);
+    memcpy(zbar, z, n * sizeof(double));
+    int64_t nprox = 0;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        int64_t k = P->k0 + kk;
+        for (size_t i = 0; i < n; ++i) {
+            w[i] = x[i] - sigma * zbar[i];
+            xhat[i] = w[i] + sigma * h[i];
+        }
+        int th = orc_coin(P->seed, P->stream_id, k, p);
+        if (th) {
+            for (size_t i = 0; i < n; ++i) v[i] = w[i] + coef * h[i];
+            orc_fgp(H, W, v, lam, P->inner_iters, P->nonneg, q, xn);
+            for (size_t i = 0; i < n; ++i) h[i] = h[i] + rate * (xn[i] - xhat[i]);
+            ++nprox;
+        } else {
+            memcpy(xn, xhat, n * sizeof(double));
+        }
+        memcpy(x, xn, n * sizeof(double));
+        int j = orc_subset(P->seed, P->stream_id, k, n_sub);
+        orc_subset_apply(A, n_sub, j, x, kx);
+        int r = 0;
+        for (int a = j; a < A->n_ang; a += n_sub, ++r) {
+            for (int d = 0; d < nd; ++d) {
+                size_t o = (size_t)a * nd + d, oj = (size_t)r * nd + d;
+                double yn = (y[o] + tau * (kx[oj] - b[o])) / (1.0 + tau);
+                dy[oj] = yn - y[o];
+                y[o] = yn;
+            }
+        }
+        orc_subset_adjoint(A, n_sub, j, dy, delta);
+        for (size_t i = 0; i < n; ++i) {
+            z[i] = z[i] + delta[i];
+            zbar[i] = z[i] + (double)n_sub * delta[i];
+        }
+        if (theta_trace) theta_trace[kk] = (uint8_t)th;
+        if (subset_trace) subset_trace[kk] = j;
+        if (obj_trace) obj_trace[kk] = orc_objective(A, b, x, P->alpha);
+    }
+    free(z); free(zbar); free(w); free(xhat); free(v); free(xn); free(delta); free(kx); free(dy);
+    return nprox;
+}
+
 /* PDHG (Chambolle-Pock), primal step first, in the same notation:
  *   x_{k+1} = prox_{sigma g}(x_k - sigma K^T y_k);  xbar = 2 x_{k+1} - x_k;
  *   y_{k+1} = (y_k + tau (K xbar - b)) / (1 + tau). */

@@ -90,6 +90,24 @@ int64_t orc_pdhgskip(const orc_op* A, const double* b, double* x, double* h,
 void orc_pdhg(const orc_op* A, const double* b, double* x, double* y,
               double* q, const orc_params* P, double* obj_trace);
 
+/* Stochastic angle subsets (the paper's "Discussion and Future work"):
+ * subset j of n holds the angles a with a mod n = j; the subset drawn at
+ * outer iteration k is orc_subset(seed, stream_id, k, n), uniform on
+ * {0, ..., n-1}, from the coin's generator on stream stream_id xor 2^63. */
+int orc_subset(uint64_t seed, uint64_t stream_id, int64_t k, int n);
+/* The rows of A (Joseph) for angle subset j of n: y_j has
+ * ceil((n_ang - j) / n) rows, row i = angle j + i n. */
+void orc_subset_apply(const orc_op* A, int n, int j, const double* x, double* yj);
+void orc_subset_adjoint(const orc_op* A, int n, int j, const double* yj, double* x);
+/* SPDHG (Chambolle, Ehrhardt, Richtarik, Schoenlieb 2018) over angle subsets
+ * with the prox of g skipped as in Alg. "PDHGSkip-2".  y (full sinogram, in
+ * natural angle order), x, h, q are in/out; every call starts from
+ * z = zbar = A^T y.  subset_trace (nullable) gets j_k.  Returns the number
+ * of prox calls. */
+int64_t orc_spdhgskip(const orc_op* A, const double* b, int n_sub, double* x, double* h,
+                      double* y, double* q, const orc_params* P, uint8_t* theta_trace,
+                      int32_t* subset_trace, double* obj_trace);
+
 /* Operator norm by power iteration on A^T A from a seeded start vector. */
 double orc_op_norm(const orc_op* A, int iters, uint64_t seed);
 
