@@ -22,7 +22,26 @@ the CPU oracle only:
 
 The trajectory tail is stored so a reader can judge the convergence.
 
-  OMP_NUM_THREADS=6 python tests/golden/make_phi_star.py [--workload ct512]
+Cross-check (--cross-check, ct512 and deblur512): a second float64 method and
+a duality certificate, both stored under "cross_check":
+
+- the oracle's explicit diagonally preconditioned PDHG on K = [A; D] with
+  closed-form proxes (the reference method of the paper's CT section), no
+  inner solver, started from the first method's end point and its duals
+  (y1 = the data dual, y2 = the prox dual divided by the prox step: the
+  saddle point of the first method's fixed point), run in chunks of 1000
+  iterations until Phi changes by less than 1e-10 relative over a chunk;
+- a certificate of the unconstrained problem min 1/2|Au - b|^2 + alpha TV(u)
+  (a lower bound of the u >= 0 problem too): y1 = A x - b shifted so that
+  A^T y1 sums to zero (the range of div), y2 = the explicit method's dual
+  plus D phi with div D phi = A^T y1 - div y2 solved exactly by the DCT-II
+  (which diagonalises the Neumann Laplacian D^T D), then both scaled by
+  s = min(1, alpha / max|y2_i|) so that |y2_i| <= alpha.  Weak duality:
+  Phi* >= -s^2 |y1|^2 / 2 - s <y1, b> + <r, u*>, r the rounding residual of
+  A^T y1 - div y2 (bounded by |r| |x| (1 + 1e-3)); Phi* <= Phi(x) for the
+  feasible end point x.
+
+  OMP_NUM_THREADS=6 python tests/golden/make_phi_star.py [--workload ct512] [--cross-check]
 """
 import argparse
 import json
@@ -34,6 +53,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
+import scipy.fft  # noqa: E402
 
 import oracle as O  # noqa: E402
 import synth  # noqa: E402
@@ -91,7 +111,7 @@ def deblur512(a):
         print(f"{done} iterations, {time.time() - t0:.0f} s: Phi = {phi:.12e}", flush=True)
         if len(traj) >= 2 and abs(traj[-2][1] - phi) <= a.tol * phi:
             break
-    return {
+    out = {
         "phi_star": traj[-1][1],
         "workload": "deblur512",
         "method": f"oracle PGD (ProxSkip at p=1), step 1, FGP {a.inner} inner iterations, "
@@ -99,6 +119,92 @@ def deblur512(a):
         "iterations": done,
         "last_chunk_rel_change": abs(traj[-2][1] - traj[-1][1]) / traj[-1][1] if len(traj) > 1 else None,
         "trajectory": traj[-12:],
+    }
+    if a.cross_check:
+        # PGD's fixed point: x = prox(x - A^T(Ax - b)) = x - A^T(Ax - b) + div q,
+        # so y1 = Ax - b, y2 = q / step (step 1) is its saddle point
+        out["certificate_first_method"] = certificate(A, b, w.alpha, x, O.proj_ball(q, w.alpha))
+        cross_check(out, A, b, w.alpha, 0, x, A.apply(x) - b, q, a, "deblur512")
+    return out
+
+
+def neumann_poisson(e):
+    """phi with D^T D phi = e (e of zero sum; the zero mode of phi is 0):
+    the DCT-II diagonalises D^T D with eigenvalues 4 sin^2(pi k / 2H) +
+    4 sin^2(pi l / 2W)."""
+    H, W = e.shape
+    k = np.arange(H)[:, None]
+    l_ = np.arange(W)[None, :]
+    lam = 4 * np.sin(np.pi * k / (2 * H)) ** 2 + 4 * np.sin(np.pi * l_ / (2 * W)) ** 2
+    ehat = scipy.fft.dctn(e, type=2, norm="ortho")
+    lam[0, 0] = 1.0
+    ph = ehat / lam
+    ph[0, 0] = 0.0
+    return scipy.fft.idctn(ph, type=2, norm="ortho")
+
+
+def certificate(A, b, alpha, x, y2):
+    """[lower, upper] bracket of the minimum of 1/2|Au - b|^2 + alpha TV(u)
+    (u >= 0 or not) from a feasible point x (>= 0 where the problem asks it)
+    and a dual estimate y2 of the TV term (|y2_i| <= alpha)."""
+    y1 = A.apply(x) - b
+    w = A.apply(np.ones_like(x))
+    y1 = y1 - (np.vdot(y1, w) / np.vdot(w, w)) * w     # sum of A^T y1 = <y1, A 1> = 0
+    g = A.adjoint(y1)
+    e = g - O.div(y2)
+    e = e - e.mean()                                   # rounding only: both sides sum to 0
+    phi = neumann_poisson(-e)                          # div D phi = -D^T D phi = e
+    y2c = y2 + O.grad(phi)
+    nrm = np.sqrt(y2c[0] ** 2 + y2c[1] ** 2).max()
+    s = min(1.0, alpha / nrm)
+    y1s, y2s = s * y1, s * y2c
+    r = A.adjoint(y1s) - O.div(y2s)
+    dual = -0.5 * np.vdot(y1s, y1s) - np.vdot(y1s, b)
+    slack = np.linalg.norm(r) * np.linalg.norm(x) * (1 + 1e-3)
+    upper = O.objective(A, b, x, alpha)
+    return {"lower": float(dual - slack), "upper": float(upper), "scale": float(s),
+            "residual_norm": float(np.linalg.norm(r)), "dual_value": float(dual)}
+
+
+def explicit_cross_check(A, b, alpha, nonneg, x, y1, y2, max_iters, label):
+    """Explicit preconditioned PDHG from (x, y1, y2) in chunks of 1000
+    iterations until Phi changes by less than 1e-10 relative over a chunk."""
+    traj = [(0, O.objective(A, b, x, alpha))]
+    done = 0
+    t0 = time.time()
+    while done < max_iters:
+        r = O.pdhg_explicit(A, b, alpha, nonneg, 1000, x=x, y1=y1, y2=y2)
+        x, y1, y2 = r["x"], r["y1"], r["y2"]
+        done += 1000
+        traj.append((done, O.objective(A, b, x, alpha)))
+        print(f"{label}: explicit PDHG {done} iterations, {time.time() - t0:.0f} s: "
+              f"Phi = {traj[-1][1]:.12e}", flush=True)
+        if abs(traj[-2][1] - traj[-1][1]) <= 1e-10 * traj[-1][1]:
+            break
+    return x, y1, y2, traj
+
+
+def cross_check(out, A, b, alpha, nonneg, x, y1, y2, a, label):
+    x2, y1e, y2e, traj = explicit_cross_check(A, b, alpha, nonneg, x.copy(), y1.copy(),
+                                              O.proj_ball(y2, alpha), a.max_explicit, label)
+    cert = certificate(A, b, alpha, x2, y2e)
+    phi1, phi2 = out["phi_star"], traj[-1][1]
+    print(f"{label}: Phi1 = {phi1:.12e}, explicit Phi2 = {phi2:.12e} "
+          f"(rel {abs(phi1 - phi2) / phi2:.2e}); certificate [{cert['lower']:.12e}, "
+          f"{cert['upper']:.12e}] (width {(cert['upper'] - cert['lower']) / phi2:.2e} rel, "
+          f"scale {cert['scale']:.12f})", flush=True)
+    out["cross_check"] = {
+        "method": "oracle explicit diagonally preconditioned PDHG on K = [A; D] "
+                  "(closed-form proxes, no inner solver), float64, started from the "
+                  "first method's end point and duals, chunks of 1000 iterations until "
+                  "Phi changes by less than 1e-10 relative over a chunk",
+        "phi_star": phi2,
+        "iterations": traj[-1][0],
+        "last_chunk_rel_change": abs(traj[-2][1] - traj[-1][1]) / traj[-1][1],
+        "rel_diff_to_first_method": abs(phi1 - phi2) / phi2,
+        "min_x": float(x2.min()),
+        "trajectory": traj[-12:],
+        "certificate": cert,
     }
 
 
@@ -112,11 +218,14 @@ def main():
     ap.add_argument("--fgp-chunk", type=int, default=2000)
     ap.add_argument("--max-fgp", type=int, default=400000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--cross-check", action="store_true")
+    ap.add_argument("--max-explicit", type=int, default=40000)
     a = ap.parse_args()
     out_path = a.out or os.path.join(HERE, f"phi_star_{a.workload}.json")
     if a.workload != "ct512":
         out = denoise128(a) if a.workload == "denoise128" else deblur512(a)
-        out["generated_by"] = (f"tests/golden/make_phi_star.py --workload {a.workload} "
+        flag = " --cross-check" if a.cross_check else ""
+        out["generated_by"] = (f"tests/golden/make_phi_star.py --workload {a.workload}{flag} "
                                "(calls only oracle/ and synth/)")
         json.dump(out, open(out_path, "w"), indent=1)
         print("wrote", out_path, flush=True)
@@ -154,6 +263,13 @@ def main():
         "trajectory": traj[-12:],
         "generated_by": "tests/golden/make_phi_star.py (calls only oracle/ and synth/)",
     }
+    if a.cross_check:
+        # PDHG's fixed point: div q = sigma A^T y, so y2 = q / sigma = L q
+        y2 = O.proj_ball(q * L, w.alpha)
+        out["certificate_first_method"] = certificate(A, b, w.alpha, x, y2)
+        cross_check(out, A, b, w.alpha, 1, x, y, y2, a, "ct512")
+        out["generated_by"] = ("tests/golden/make_phi_star.py --cross-check "
+                               "(calls only oracle/ and synth/)")
     json.dump(out, open(out_path, "w"), indent=1)
     print("wrote", out_path, flush=True)
 

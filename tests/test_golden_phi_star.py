@@ -8,9 +8,17 @@ written by tests/golden/make_phi_star.py from the CPU oracle only).
 - ct512 / deblur512: Phi* is a minimum, so it cannot exceed the objective at
   the zero image; the stored trajectory must be non-increasing at its end
   and its last chunk must have changed by less than the stopping tolerance.
+  A second float64 method (the oracle's explicit diagonally preconditioned
+  PDHG, no inner solver) must agree to 1e-7 relative after meeting its own
+  stopping rule, and the stored value must lie inside the weak-duality
+  bracket written beside it (a dual point made exactly feasible).
+- The bracket itself (make_phi_star.certificate) on a small CT problem: it
+  contains the objective of a long run and is tight there, and at a
+  perturbed point its width is at least the perturbation's excess.
 """
 import json
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -19,6 +27,8 @@ import oracle as O
 import synth
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
 
 
 def load(name):
@@ -63,3 +73,47 @@ def test_minimum_below_zero_image_and_converged(name):
     tail = [v for _, v in d["trajectory"]]
     assert tail[-1] == phi and all(a >= b_ for a, b_ in zip(tail, tail[1:]))
     assert d["last_chunk_rel_change"] < 1e-6
+
+
+@pytest.mark.parametrize("name", ["ct512", "deblur512"])
+def test_second_method_agrees_and_bracket_holds(name):
+    d = load(name)
+    if "cross_check" not in d:
+        pytest.skip("cross-check not generated")
+    cc = d["cross_check"]
+    phi = d["phi_star"]
+    assert cc["last_chunk_rel_change"] <= 1e-10
+    assert abs(cc["phi_star"] - phi) <= 1e-7 * phi
+    assert cc["rel_diff_to_first_method"] == pytest.approx(abs(cc["phi_star"] - phi) / cc["phi_star"])
+    cert = cc["certificate"]
+    assert cert["lower"] <= phi <= cert["upper"] + 1e-12 * phi
+    # both stored minima are objective values at feasible points, so the
+    # smaller is the better upper bound; the bracket's lower end is below it
+    assert cert["lower"] <= min(phi, cc["phi_star"])
+
+
+@pytest.mark.slow
+def test_certificate_brackets_and_detects_a_perturbation():
+    from make_phi_star import certificate
+    N, na, nd = 24, 20, 35
+    ang = synth.parallel_beam_angles(na)
+    A = O.joseph(N, N, ang, nd, 2.0 / N, 2.0 / N)
+    u, eta = synth.phantom_and_noise(N, N, 6, 5, (na, nd))
+    Au = A.apply(u)
+    b = synth.to_f32_exact(Au + 0.01 * Au.max() * eta)
+    alpha = 0.05
+    L = A.norm(300)
+    r = O.pdhg(A, b, alpha, 1 / L, 1 / L, 4000, 200, nonneg=1)
+    x, y, q = r["x"], r["y"], r["q"]
+    r2 = O.pdhg_explicit(A, b, alpha, 1, 20000, x=x.copy(), y1=y.copy(),
+                         y2=O.proj_ball(q * L, alpha))
+    c = certificate(A, b, alpha, r2["x"], r2["y2"])
+    phi_long = O.objective(A, b, x, alpha)
+    assert c["lower"] <= phi_long + 1e-12 and c["lower"] <= c["upper"]
+    assert c["upper"] - c["lower"] <= 1e-7 * c["upper"]
+    # a perturbed point: the bracket's upper end rises by the excess, the
+    # lower end stays below the minimum
+    xp = np.maximum(r2["x"] + 0.01 * np.random.default_rng(0).standard_normal(x.shape), 0)
+    cp = certificate(A, b, alpha, xp, r2["y2"])
+    assert cp["lower"] <= phi_long + 1e-12
+    assert cp["upper"] - cp["lower"] >= O.objective(A, b, xp, alpha) - phi_long - 1e-9

@@ -182,6 +182,18 @@ def test_coin_edges():
     assert O.mix64(0) == 0
 
 
+def test_splitmix64_published_outputs():
+    """SplitMix64 (Steele, Lea and Flood 2014) started from state 0 adds the
+    golden-ratio increment before each output and returns the mix of the new
+    state; its first outputs are the published 0xE220A8397B1DCDAF,
+    0x6E789E6AA1B965F4, 0x06C45D188009454F.  A mix with a wrong shift or
+    multiplier fails this (it would still map 0 to 0)."""
+    g = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    got = [O.mix64((k * g) & 0xFFFFFFFFFFFFFFFF) for k in (1, 2, 3)]
+    assert got == want
+
+
 def test_coin_counts_like_the_paper_table():
     """The paper's prox counts are Binomial(iterations, p) draws of its own
     coin; ours over the same iteration counts lands in the same range.
