@@ -18,6 +18,13 @@ Parity status of each function (what pins it lives in tests/test_oracle_*.py):
   coin ............................ pinned (published SplitMix64 outputs of
                                      state 0, Bernoulli and run statistics)
   op_norm ......................... pinned (identity, blur = 1, SVD of small A)
+  fista ........................... pinned (first call step equals one PGD
+                                     step bitwise; momentum sequence against a
+                                     separate t-recursion on A = I quadratics;
+                                     converges to PGD's minimum)
+  pdhgskip1 ....................... pinned (p = 1 equals the separately
+                                     written PDHG bitwise; skipped iterations
+                                     leave x bitwise; same minimum as PDHG)
   subset, subset_apply/adjoint .... pinned (uniform counts, pure function of
                                      (seed, stream, k); the rows of the full A)
   spdhgskip ....................... pinned (untouched subsets keep their rows
@@ -100,6 +107,9 @@ def lib():
         L.orc_pdhgskip.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, dp, C.POINTER(OrcParams), u8p, dp]
         L.orc_pdhgskip.restype = C.c_int64
         L.orc_pdhg.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, C.POINTER(OrcParams), dp]
+        L.orc_fista.argtypes = [C.POINTER(OrcOp), dp, dp, dp, C.POINTER(OrcParams), dp]
+        L.orc_pdhgskip1.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, C.POINTER(OrcParams), u8p, dp]
+        L.orc_pdhgskip1.restype = C.c_int64
         L.orc_subset.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int]
         L.orc_subset.restype = C.c_int
         L.orc_subset_apply.argtypes = [C.POINTER(OrcOp), C.c_int, C.c_int, dp, dp]
@@ -316,6 +326,32 @@ def pdhg(A: Op, b, alpha, sigma, tau, outer, inner, nonneg=0, x=None, y=None, q=
     lib().orc_pdhg(C.byref(A.s), _p(b), _p(x), _p(y), _p(q), C.byref(P),
                    _p(obj) if want_obj else None)
     return dict(x=x, y=y, q=q, obj=obj)
+
+
+def fista(A: Op, b, alpha, step, outer, inner, nonneg=0, x=None, q=None, want_obj=False):
+    """Alg. FISTA (Beck-Teboulle momentum) with the FGP prox; the momentum
+    restarts at every call.  Returns dict(x, q, obj)."""
+    b = _f64(b)
+    x, q = _state(x, (A.H, A.W)), _state(q, (2, A.H, A.W))
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, step, 0.0, 1.0, outer, inner, nonneg, 0, 0, 0)
+    lib().orc_fista(C.byref(A.s), _p(b), _p(x), _p(q), C.byref(P), _p(obj) if want_obj else None)
+    return dict(x=x, q=q, obj=obj)
+
+
+def pdhgskip1(A: Op, b, alpha, sigma, tau, p, outer, inner, nonneg=0, seed=0, stream=0, k0=0,
+              x=None, y=None, q=None, want_obj=False):
+    """Alg. PDHGSkip-1 (omega + 1 = 1/p).  Returns dict(x, y, q, theta, obj, nprox)."""
+    b = _f64(b)
+    x, q = _state(x, (A.H, A.W)), _state(q, (2, A.H, A.W))
+    y = _state(y, A.out_shape)
+    theta = np.zeros(outer, dtype=np.uint8)
+    obj = np.zeros(outer) if want_obj else None
+    P = _params(alpha, sigma, tau, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_pdhgskip1(C.byref(A.s), _p(b), _p(x), _p(y), _p(q), C.byref(P),
+                            theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                            _p(obj) if want_obj else None)
+    return dict(x=x, y=y, q=q, theta=theta, obj=obj, nprox=int(n))
 
 
 def subset(seed, stream, k, n) -> int:

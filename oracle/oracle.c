@@ -625,6 +625,93 @@ int64_t orc_spdhgskip(const orc_op* A, const double* b, int n_sub, double* x, do
     return nprox;
 }
 
+/* ------------------------------------------------------------------------
+ * Alg. "FISTA" with the FGP prox.  The printed momentum (a_k = t_{k-1} /
+ * t_{k+1} and x_k - x_{k+1}) is read as Beck and Teboulle's (t_k - 1) /
+ * t_{k+1} applied to x_k - x_{k-1}:
+ *   xbar = x_k + beta_k (x_k - x_{k-1}),  beta_k = (t_k - 1) / t_{k+1},
+ *   x_{k+1} = prox_{gamma g}(xbar - gamma A^T (A xbar - b)),
+ * t_1 = 1 and x_0 = x_{-1} = x at the start of each call (so beta_1 = 0,
+ * the first step is a plain proximal gradient step).
+ * ------------------------------------------------------------------------ */
+void orc_fista(const orc_op* A, const double* b, double* x, double* q,
+               const orc_params* P, double* obj_trace) {
+    int H = A->H, W = A->W;
+    size_t n = (size_t)H * W, m = orc_op_out_size(A);
+    double gamma = P->step, lam = P->alpha * P->step;
+    double* xprev = dalloc(n);
+    double* xbar = dalloc(n);
+    double* g = dalloc(n);
+    double* v = dalloc(n);
+    double* xn = dalloc(n);
+    double* res = dalloc(m);
+    memcpy(xprev, x, n * sizeof(double));
+    double t = 1.0;
+    for (int64_t k = 0; k < P->outer_iters; ++k) {
+        double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        double beta = (t - 1.0) / tn;
+        for (size_t i = 0; i < n; ++i) xbar[i] = x[i] + beta * (x[i] - xprev[i]);
+        data_grad(A, b, xbar, res, g);
+        for (size_t i = 0; i < n; ++i) v[i] = xbar[i] - gamma * g[i];
+        orc_fgp(H, W, v, lam, P->inner_iters, P->nonneg, q, xn);
+        memcpy(xprev, x, n * sizeof(double));
+        memcpy(x, xn, n * sizeof(double));
+        t = tn;
+        if (obj_trace) obj_trace[k] = orc_objective(A, b, x, P->alpha);
+    }
+    free(xprev); free(xbar); free(g); free(v); free(xn); free(res);
+}
+
+/* ------------------------------------------------------------------------
+ * Alg. "PDHGSkip-1" (the skipped PDHG of Condat et al. that the paper
+ * compares with): B_p(z) = z / p with probability p, else 0;
+ *   xhat_k = B_p(prox_{sigma g}(x_k - sigma K^T y_k) - x_k)
+ *   x_{k+1} = x_k + xhat_k / (1 + omega),  omega + 1 = 1/p (the paper's choice)
+ *   y_{k+1} = prox_{tau f*}(y_k + tau K(x_{k+1} + xhat_k))   (bracket read as
+ *             K applied to x_{k+1} + xhat_k).
+ * With omega + 1 = 1/p, x_{k+1} = prox(...) when theta_k = 1 and x_k
+ * otherwise; x_{k+1} + xhat_k = (1 + 1/p) x+ - x_k / p, which is 2 x+ - x_k
+ * bit for bit at p = 1, so the method is PDHG there.  On skipped iterations
+ * neither K^T y nor the prox is needed.
+ * ------------------------------------------------------------------------ */
+int64_t orc_pdhgskip1(const orc_op* A, const double* b, double* x, double* y,
+                      double* q, const orc_params* P, uint8_t* theta_trace,
+                      double* obj_trace) {
+    int H = A->H, W = A->W;
+    size_t n = (size_t)H * W, m = orc_op_out_size(A);
+    double sigma = P->step, tau = P->dual_step, p = P->p;
+    double lam = P->alpha * sigma;
+    double c1 = 1.0 + 1.0 / p, c2 = 1.0 / p;
+    double* kty = dalloc(n);
+    double* w = dalloc(n);
+    double* xn = dalloc(n);
+    double* e = dalloc(n);
+    double* ke = dalloc(m);
+    int64_t nprox = 0;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        int64_t k = P->k0 + kk;
+        int th = orc_coin(P->seed, P->stream_id, k, p);
+        if (th) {
+            orc_op_adjoint(A, y, kty);
+            for (size_t i = 0; i < n; ++i) w[i] = x[i] - sigma * kty[i];
+            orc_fgp(H, W, w, lam, P->inner_iters, P->nonneg, q, xn);
+            for (size_t i = 0; i < n; ++i) {
+                e[i] = c1 * xn[i] - c2 * x[i];
+                x[i] = xn[i];
+            }
+            ++nprox;
+        } else {
+            memcpy(e, x, n * sizeof(double));
+        }
+        orc_op_apply(A, e, ke);
+        for (size_t i = 0; i < m; ++i) y[i] = (y[i] + tau * (ke[i] - b[i])) / (1.0 + tau);
+        if (theta_trace) theta_trace[kk] = (uint8_t)th;
+        if (obj_trace) obj_trace[kk] = orc_objective(A, b, x, P->alpha);
+    }
+    free(kty); free(w); free(xn); free(e); free(ke);
+    return nprox;
+}
+
 /* PDHG (Chambolle-Pock), primal step first, in the same notation:
  *   x_{k+1} = prox_{sigma g}(x_k - sigma K^T y_k);  xbar = 2 x_{k+1} - x_k;
  *   y_{k+1} = (y_k + tau (K xbar - b)) / (1 + tau). */

@@ -108,6 +108,23 @@ int64_t orc_spdhgskip(const orc_op* A, const double* b, int n_sub, double* x, do
                       double* y, double* q, const orc_params* P, uint8_t* theta_trace,
                       int32_t* subset_trace, double* obj_trace);
 
+/* Alg. "FISTA" (read as Beck and Teboulle's: t_{k+1} = (1 + sqrt(1 + 4
+ * t_k^2)) / 2, xbar = x_k + ((t_k - 1) / t_{k+1})(x_k - x_{k-1}),
+ * x_{k+1} = prox_{gamma g}(xbar - gamma grad f(xbar))) with the same FGP
+ * prox, warm started.  Every call restarts the momentum (t_1 = 1,
+ * x_{k-1} = x_k).  x, q in/out. */
+void orc_fista(const orc_op* A, const double* b, double* x, double* q,
+               const orc_params* P, double* obj_trace);
+/* Alg. "PDHGSkip-1" (Condat et al.'s skipped PDHG, with the bracket read as
+ * K(x_{k+1} + xhat_k) and omega + 1 = 1/p):
+ *   theta_k = 1: x+ = prox_{sigma g}(x_k - sigma K^T y_k); else x+ = x_k;
+ *   e = x_{k+1} + xhat_k = (1 + 1/p) x+ - x_k / p (theta_k = 1), x_k (theta_k = 0);
+ *   y_{k+1} = (y_k + tau (K e - b)) / (1 + tau).
+ * x, y, q in/out.  Returns the number of prox calls. */
+int64_t orc_pdhgskip1(const orc_op* A, const double* b, double* x, double* y,
+                      double* q, const orc_params* P, uint8_t* theta_trace,
+                      double* obj_trace);
+
 /* Operator norm by power iteration on A^T A from a seeded start vector. */
 double orc_op_norm(const orc_op* A, int iters, uint64_t seed);
 
