@@ -132,9 +132,10 @@ def main():
         f"{rep['n_prox']} prox per solve")
 
     # ---- time to 1e-4 relative objective (deterministic replay for Phi)
-    tta = small = None
+    tta = small = spdhg = None
     if not args.no_tta:
         tta = time_to_accuracy(solve, w, K)
+        spdhg = spdhg_tta(T, ctx, w, b, seed)
         small = small_tta(T, ctx)
 
     # ---- per-kernel timing with HIP events on the context's stream
@@ -190,8 +191,9 @@ def main():
                    "outer_iters_per_step": K, "prox_per_step": rep["n_prox"],
                    "fgp_variant": list(T.tvs_fgp_variant(best)), "norm_A": Lnorm},
         "time_to_1e-4": tta,
+        "time_to_1e-4_angle_subsets": spdhg,
         "time_to_1e-4_denoise_deblur": small,
-        "kernels_ms_per_step": {k: round(v, 4) for k, v in kern["per_step_ms"].items()},
+        "kernels_ms_per_step": trace_per_step(K),
         "roofline": roof,
         "tv_prox_hbm": fgp_big,
         "batched": batched,
@@ -202,43 +204,100 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_to_accuracy(solve, w, K):
-    """k* = first outer iteration after which |Phi(x_k) - Phi*| / Phi* stays
-    <= 1e-4 (Phi from an instrumented replay of the same deterministic run);
-    the time is that of an un-instrumented run of exactly k* iterations."""
+def tta_entry(run, K, phis, name):
+    """Time to 1e-4 of one method: k* = first outer iteration after which
+    |Phi(x_k) - Phi*| / Phi* stays <= 1e-4, Phi from an instrumented replay
+    of the same deterministic run (run(iters, obj=True)); the time is the
+    median HIP-event time of three un-instrumented graph runs of exactly k*
+    iterations (run(iters))."""
     import numpy as np
     import torch
+    r = run(K, obj=True)
+    rel = np.abs(r["obj"] - phis) / phis
+    bad = np.nonzero(rel > 1e-4)[0]
+    kstar = int(bad[-1] + 2) if len(bad) else 1
+    if kstar > K:
+        return {"iters": None, "note": f"not reached in {K} iterations",
+                "final_rel": float(rel[-1])}
+    times = []
+    for _ in range(3):
+        run(kstar)  # capture / warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(kstar)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    out = {"iters": kstar, "ms": round(float(np.median(times)), 3),
+           "prox_calls": int(np.sum(r["theta"][:kstar])), "final_rel": float(rel[-1])}
+    log(f"time to 1e-4 ({name}): {kstar} iterations, {out['ms']:.2f} ms")
+    return out
+
+
+def time_to_accuracy(solve, w, K, p_sweep=(0.1, 0.3, 0.5, 0.7)):
+    """Time to 1e-4 on the CT workload: PDHGSkip-2 at the workload's p, the
+    p sweep, and PDHG (p = 1)."""
     path = os.path.join(ROOT, "tests", "golden", "phi_star_ct512.json")
     if not os.path.exists(path):
         return {"note": "reference minimum Phi* not available"}
     phis = json.load(open(path))["phi_star"]
     res = {"phi_star": phis}
-    for name, pp in (("pdhgskip_p0.1", w.p), ("pdhg_p1", 1.0)):
-        r = solve(pp=pp, iters=K, obj=True)
-        obj = r["obj"]
-        rel = np.abs(obj - phis) / phis
-        bad = np.nonzero(rel > 1e-4)[0]
-        kstar = int(bad[-1] + 2) if len(bad) else 1
-        if kstar > K:
-            res[name] = {"iters": None, "note": f"not reached in {K} iterations",
-                         "final_rel": float(rel[-1])}
-            continue
-        times = []
-        for _ in range(3):
-            solve(pp=pp, iters=kstar)  # capture / warm
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            solve(pp=pp, iters=kstar)
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        res[name] = {"iters": kstar, "ms": round(float(np.median(times)), 3),
-                     "prox_calls": int(np.sum(r["theta"][:kstar])),
-                     "final_rel": float(rel[-1])}
-        log(f"time to 1e-4 ({name}): {kstar} iterations, {np.median(times):.2f} ms")
-    if res.get("pdhgskip_p0.1", {}).get("ms") and res.get("pdhg_p1", {}).get("ms"):
-        res["speedup_pdhgskip_vs_pdhg"] = round(res["pdhg_p1"]["ms"] / res["pdhgskip_p0.1"]["ms"], 3)
+    for pp in sorted(set(p_sweep) | {w.p}) + [1.0]:
+        name = "pdhg_p1" if pp == 1.0 else f"pdhgskip_p{pp}"
+        res[name] = tta_entry(lambda iters, obj=False: solve(pp=pp, iters=iters, obj=obj), K,
+                              phis, name)
+    key = f"pdhgskip_p{w.p}"
+    if res.get(key, {}).get("ms") and res.get("pdhg_p1", {}).get("ms"):
+        res["speedup_pdhgskip_vs_pdhg"] = round(res["pdhg_p1"]["ms"] / res[key]["ms"], 3)
+    return res
+
+
+def spdhg_tta(T, ctx, w, b, seed, K=6000, configs=((4, 0.1), (4, 0.3), (10, 0.1), (10, 0.3),
+                                                      (10, 1.0))):
+    """Time to 1e-4 on the CT workload with random angle subsets (SPDHG over
+    n interleaved subsets with the skipped prox): per (n, p), step sizes
+    sigma = 0.99 / (n max_j |A_j|), tau = 0.99 / max_j |A_j| (SPDHG's
+    condition sigma tau |A_j|^2 < 1/n), norms of the subset operators by 100
+    power iterations on the GPU."""
+    import torch
+    import synth
+    path = os.path.join(ROOT, "tests", "golden", "phi_star_ct512.json")
+    if not os.path.exists(path):
+        return {"note": "reference minimum Phi* not available"}
+    phis = json.load(open(path))["phi_star"]
+    dev = torch.device("cuda:0")
+    N, na, nd = w.H, w.n_ang, w.n_det
+    ang = synth.parallel_beam_angles(na)
+    op = T.tvs_op_ct_joseph(ctx, N, N, ang, nd, w.pixel, w.det_spacing)
+    x = torch.zeros(N, N, device=dev)
+    h = torch.zeros_like(x)
+    q = torch.zeros(2, N, N, device=dev)
+    y = torch.zeros(na, nd, device=dev)
+    res = {"phi_star": phis, "outer_iters_budget": K}
+    norms = {}
+    for n, pp in configs:
+        if n not in norms:
+            m = 0.0
+            for j in range(n):
+                sop = T.tvs_op_ct_joseph(ctx, N, N, ang[j::n], nd, w.pixel, w.det_spacing)
+                m = max(m, T.tvs_op_norm(sop, 100, 1))
+                T.tvs_op_destroy(sop)
+            norms[n] = m
+        m = norms[n]
+        sigma, tau = 0.99 / (n * m), 0.99 / m
+
+        def run(iters, obj=False, n=n, pp=pp, sigma=sigma, tau=tau):
+            for t in (x, h, q, y):
+                t.zero_()
+            return T.tvs_spdhgskip(op, b, x, h, q, y, n, w.alpha, sigma, tau, pp, iters,
+                                   w.inner_iters, nonneg=1, seed=seed, graph=not obj,
+                                   want_obj=obj, want_theta=obj)
+
+        name = f"subsets{n}_p{pp}"
+        res[name] = tta_entry(run, K, phis, name)
+        res[name].update({"sigma": sigma, "tau": tau, "max_subset_norm": m})
+    T.tvs_op_destroy(op)
     return res
 
 
@@ -358,6 +417,28 @@ def kernel_times(T, ctx, op, N, na, nd, Kin, n_prox, K):
 
 COPY_CAL_BYTES = 256 << 20
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "joseph_adj_ct512_pmc.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "ct512_bench_kernels.md")
+
+
+def trace_per_step(K):
+    """Milliseconds per 3000-iteration solve spent in each hot kernel, from
+    the committed rocprofv3 kernel trace of the solve (average duration in
+    the solve x launches per solve), or None when a kernel source changed
+    since the trace was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRACE_SUMMARY).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        for src, want in rec["source_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != want:
+                return None
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    if rec.get("outer_iters") != K:
+        return None
+    return {k: round(v["avg_us"] * v["launches_per_solve"] / 1e3, 3)
+            for k, v in rec["kernels"].items()}
 
 
 def measured_traffic(kernel_source, hash_key="source_sha256"):
@@ -841,19 +922,45 @@ def cpu_baseline(b, w, ang, sigma, tau, seed, target_s=12.0):
     except OSError:
         gomp = None
     if gomp is not None and threads > 1:
+        # a window whose prox rate is the run's: the first n >= 10 iterations
+        # with a coin count within 30 % of p n
+        theta = [O.coin(seed, 0, k, w.p) for k in range(200)]
+        n1, cnt = 10, sum(theta[:10])
+        while n1 < 200 and abs(cnt - w.p * n1) > 0.3 * w.p * n1:
+            cnt += theta[n1]
+            n1 += 1
         gomp.omp_set_num_threads(1)
         try:
-            n1 = max(2, min(40, int(4.0 / max(per * threads, 1e-3))))
             t0 = time.perf_counter()
             r1 = O.pdhgskip(A, b, w.alpha, sigma, tau, w.p, n1, w.inner_iters, nonneg=1, seed=seed)
             el1 = time.perf_counter() - t0
         finally:
             gomp.omp_set_num_threads(threads)
         out["single_thread"] = {"value": round(n1 / el1, 4),
-                                "sample": f"first {n1} outer iterations ({r1['nprox']} prox calls)",
+                                "sample": f"first {n1} outer iterations ({r1['nprox']} prox calls, "
+                                          f"the run's prox rate {w.p})",
                                 "seconds": round(el1, 2)}
-        log(f"CPU oracle, one thread: {n1} iterations in {el1:.2f} s")
+        log(f"CPU oracle, one thread: {n1} iterations in {el1:.2f} s ({r1['nprox']} prox)")
+    out["host_cpu"] = host_cpu()
     return out
+
+
+def host_cpu():
+    """CPU model and the cores this process may use (from /proc/cpuinfo and
+    the scheduler affinity)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 if __name__ == "__main__":

@@ -103,6 +103,18 @@ tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
                             const double* angles_host, int n_det, double pixel,
                             double det_spacing, tvs_op** out);
 
+/* Angle groups of the float32 ray-driven backprojector of a Joseph operator
+ * (a tuning control; the result does not depend on it beyond the order of
+ * the float32 sums): one workgroup per (52 x 52 tile, group), group g
+ * holding angles g, g + groups, ...; the groups' partial images are summed in
+ * a fixed order.  groups = 0 restores the automatic choice (the count that
+ * balances the most loaded compute unit).  Otherwise 1 <= ceil(n_ang / 36)
+ * <= groups <= n_ang (TVS_ERR_INVALID_ARG; also for an operator that is not
+ * Joseph).  Waits for the device and drops the context's captured graphs. */
+tvs_status tvs_op_joseph_set_groups(tvs_op* op, int groups);
+/* The group count the backprojector uses (-1 if op is not Joseph). */
+int tvs_op_joseph_groups(const tvs_op* op);
+
 void tvs_op_destroy(tvs_op* op);
 /* Output size (number of elements of Y). */
 size_t tvs_op_out_size(const tvs_op* op);
@@ -259,6 +271,35 @@ tvs_status tvs_proxskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
 tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
                         const tvs_params* params, double* obj_trace,
                         uint8_t* theta_trace, tvs_report* report);
+
+/* Stochastic angle subsets with the skipped prox (the paper's "Discussion
+ * and Future work": a random subset of the projection angles per iteration
+ * in addition to the random prox).  Reading: SPDHG (Chambolle, Ehrhardt,
+ * Richtarik, Schoenlieb, SIAM J. Optim. 2018) over n_subsets interleaved
+ * angle subsets (subset j: angles j, j + n, ...; f_j = 1/2|. - b_j|^2,
+ * uniform sampling, dual extrapolation 1/p_j = n), with the primal prox of
+ * g skipped as in PDHGSkip-2:
+ *   xhat = x_k - sigma (zbar_k - h_k)
+ *   theta_k = 1: x_{k+1} = prox_{(sigma/p) g}(xhat - (sigma/p) h_k), by FGP
+ *   theta_k = 0: x_{k+1} = xhat
+ *   h_{k+1} = h_k + (p/sigma)(x_{k+1} - xhat)
+ *   j = j_k:  y_j = (y_j + tau (A_j x_{k+1} - b_j)) / (1 + tau)
+ *   z += A_j^T dy_j;  zbar = z + n A_j^T dy_j   (dy_j: the change of y_j)
+ * with z = zbar = A^T y at the start of every call.  j_k = tvs_subset(seed,
+ * stream_id, k, n_subsets).  Step sizes (caller's choice; SPDHG's condition
+ * sigma tau |A_j|^2 < 1/n): params->step = sigma, params->dual_step = tau.
+ * Joseph operators only (TVS_ERR_UNSUPPORTED otherwise); 1 <= n_subsets <=
+ * min(n_ang, 1024) (TVS_ERR_INVALID_ARG).  state->y is required (natural
+ * angle order).  subset_trace (nullable, host, outer_iters int32): j_k.
+ * Other arguments as tvs_pdhgskip; TVS_FLAG_GRAPH captures the run. */
+tvs_status tvs_spdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                         const tvs_params* params, int n_subsets, double* obj_trace,
+                         uint8_t* theta_trace, int32_t* subset_trace, tvs_report* report);
+
+/* The angle subset drawn at outer iteration k of tvs_spdhgskip: SplitMix64
+ * as tvs_coin on the stream stream_id xor 2^63, j_k = floor((r >> 11) n /
+ * 2^53) (uniform on 0..n-1).  -1 if n < 1, n > 1024 or k < 0.  Host, pure. */
+int tvs_subset(uint64_t seed, uint64_t stream_id, int64_t k, int n);
 
 /* ------------------------------------------------ light-prox problems
  * ProxSkip on the dual of TV denoising, Sec. 2.1-2.2:

@@ -21,8 +21,10 @@ __all__ = [
     "tvs_ctx_create", "tvs_ctx_destroy", "tvs_ctx_set_stream", "tvs_sync", "tvs_last_error",
     "tvs_op_identity", "tvs_op_blur_periodic", "tvs_op_ct_joseph", "tvs_op_destroy",
     "tvs_op_out_size", "tvs_op_apply", "tvs_op_adjoint", "tvs_op_norm",
+    "tvs_op_joseph_set_groups", "tvs_op_joseph_groups",
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
+    "tvs_spdhgskip", "tvs_subset",
     "tvs_dual_rof_proxskip",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
     "tvs_proxskip_batched", "tvs_fgp_set_variant_batched", "tvs_fgp_autotune_batched",
@@ -143,6 +145,14 @@ def tvs_op_adjoint(op: int, y, x) -> None:
     check(lib().tvs_op_adjoint(C.c_void_p(op), d, _ptr(y, tvs_op_out_size(op)), _ptr(x, None, d)))
 
 
+def tvs_op_joseph_set_groups(op: int, groups: int) -> None:
+    check(lib().tvs_op_joseph_set_groups(C.c_void_p(op), int(groups)))
+
+
+def tvs_op_joseph_groups(op: int) -> int:
+    return int(lib().tvs_op_joseph_groups(C.c_void_p(op)))
+
+
 def tvs_op_norm(op: int, iters: int = 200, seed: int = 1) -> float:
     out = C.c_double()
     check(lib().tvs_op_norm(C.c_void_p(op), int(iters), int(seed), C.byref(out)))
@@ -196,6 +206,10 @@ def tvs_coin(seed: int, stream_id: int, k: int, p: float) -> int:
     return int(lib().tvs_coin(int(seed), int(stream_id), int(k), float(p)))
 
 
+def tvs_subset(seed: int, stream_id: int, k: int, n: int) -> int:
+    return int(lib().tvs_subset(int(seed), int(stream_id), int(k), int(n)))
+
+
 # ---------------------------------------------------------------- solvers
 def _solve(fn, op, b, x, h, q, y, alpha, step, dual_step, p, outer_iters, inner_iters, nonneg,
            seed, stream_id, k0, graph, want_obj, want_theta, ext=None):
@@ -247,6 +261,36 @@ def tvs_pdhgskip(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inne
     """PDHGSkip-2 in place on (x, h, q, y).  Returns dict(n_prox, iters, obj, theta)."""
     return _solve(lib().tvs_pdhgskip, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
                   inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta)
+
+
+def tvs_spdhgskip(op: int, b, x, h, q, y, n_subsets, alpha, sigma, tau, p, outer_iters,
+                  inner_iters, nonneg=0, seed=0, stream_id=0, k0=0, graph=False, want_obj=False,
+                  want_theta=False, want_subsets=False):
+    """Stochastic angle subsets with the skipped prox, in place on (x, h, q,
+    y).  Returns dict(n_prox, iters, obj, theta, subsets)."""
+    import numpy as np
+    d = _dtype_code(x)
+    n = x.numel()
+    st = tvs_state(_ptr(x), _ptr(h, n, d), _ptr(q, 2 * n, d), _ptr(y, tvs_op_out_size(op), d))
+    P = tvs_params(alpha=float(alpha), step=float(sigma), dual_step=float(tau), p=float(p),
+                   outer_iters=int(outer_iters), inner_iters=int(inner_iters),
+                   nonneg=int(nonneg), seed=int(seed), stream_id=int(stream_id), k0=int(k0),
+                   flags=TVS_FLAG_GRAPH if graph else 0, reserved=0)
+    rep = tvs_report()
+    K = max(int(outer_iters), 1)
+    obj = np.zeros(K) if want_obj else None
+    th = np.zeros(K, dtype=np.uint8) if want_theta else None
+    sub = np.zeros(K, dtype=np.int32) if want_subsets else None
+    check(lib().tvs_spdhgskip(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st),
+                              C.byref(P), int(n_subsets),
+                              obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
+                              th.ctypes.data_as(C.POINTER(C.c_uint8)) if want_theta else None,
+                              sub.ctypes.data_as(C.POINTER(C.c_int32)) if want_subsets else None,
+                              C.byref(rep)))
+    return dict(n_prox=rep.n_prox, iters=rep.iters,
+                obj=obj[:outer_iters] if want_obj else None,
+                theta=th[:outer_iters] if want_theta else None,
+                subsets=sub[:outer_iters] if want_subsets else None)
 
 
 def tvs_proxskip_ex(op: int, b, x, h, q, alpha, step, p, outer_iters, inner_iters, nonneg=0,

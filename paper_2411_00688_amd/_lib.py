@@ -81,6 +81,8 @@ PROTOTYPES = {
                                    C.c_double, C.POINTER(vp)]),
     "tvs_op_destroy": (None, [vp]),
     "tvs_op_out_size": (C.c_size_t, [vp]),
+    "tvs_op_joseph_set_groups": (C.c_int, [vp, C.c_int]),
+    "tvs_op_joseph_groups": (C.c_int, [vp]),
     "tvs_op_apply": (C.c_int, [vp, C.c_int, vp, vp]),
     "tvs_op_adjoint": (C.c_int, [vp, C.c_int, vp, vp]),
     "tvs_op_norm": (C.c_int, [vp, C.c_int, C.c_uint64, dp]),
@@ -91,6 +93,10 @@ PROTOTYPES = {
     "tvs_tv_gap": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_double, C.c_int, vp, dp, dp]),
     "tvs_objective": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp]),
     "tvs_coin": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_double]),
+    "tvs_subset": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int]),
+    "tvs_spdhgskip": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params),
+                                C.c_int, dp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32),
+                                C.POINTER(tvs_report)]),
     "tvs_proxskip": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params), dp,
                                C.POINTER(C.c_uint8), C.POINTER(tvs_report)]),
     "tvs_pdhgskip": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params), dp,

@@ -78,6 +78,16 @@ int coin(uint64_t seed, uint64_t stream, int64_t k, double p) {
     return (r >> 11) < thresh ? 1 : 0;
 }
 
+// Angle subset of the stochastic-angle method at iteration k: the coin's
+// generator on stream `stream` xor 2^63, floor((r >> 11) n / 2^53), in
+// 64-bit integer arithmetic (exact: r >> 11 < 2^53 and n < 2^10).
+int subset_draw(uint64_t seed, uint64_t stream, int64_t k, int n) {
+    if (n < 1 || n > 1024 || k < 0) return -1;
+    const uint64_t key = splitmix_mix(seed ^ splitmix_mix((stream ^ (1ULL << 63)) + kGolden));
+    const uint64_t r = splitmix_mix(key + (uint64_t)(k + 1) * kGolden);
+    return (int)(((r >> 11) * (uint64_t)n) >> 53);
+}
+
 // ---------------------------------------------------- FGP momentum table
 // beta[0] = 0 and beta[k] = (t_{k-1} - 1) / t_k, t_0 = 1,
 // t_k = (1 + sqrt(1 + 4 t_{k-1}^2)) / 2, computed once in float64.
@@ -297,13 +307,91 @@ extern "C" tvs_status tvs_op_ct_joseph(tvs_ctx* ctx, int H, int W, int n_ang,
             e.half_spanf = (float)e.half_span;
             g.host[a] = e;
         }
-        // the ray-driven float32 backprojector needs every angle to qualify
-        g.rd_ok = true;
-        for (const JAngle& e : g.host) g.rd_ok = g.rd_ok && joseph_rd_angle_ok(e);
-        TVS_HIP(hipMalloc(&g.ang, n_ang * sizeof(JAngle)));
-        TVS_HIP(hipMemcpy(g.ang, g.host.data(), n_ang * sizeof(JAngle), hipMemcpyHostToDevice));
+        joseph_upload(op.get());
         *out = op.release();
     });
+}
+
+namespace tvs {
+
+// Device tables of a Joseph operator from its host angle table: the angle
+// table, and whether the ray-driven float32 backprojector applies (every
+// angle must qualify).
+void joseph_upload(tvs_op* op) {
+    JosephGeom& g = op->joseph;
+    g.rd_ok = true;
+    for (const JAngle& e : g.host) g.rd_ok = g.rd_ok && joseph_rd_angle_ok(e);
+    TVS_HIP(hipMalloc(&g.ang, g.n_ang * sizeof(JAngle)));
+    TVS_HIP(hipMemcpy(g.ang, g.host.data(), g.n_ang * sizeof(JAngle), hipMemcpyHostToDevice));
+}
+
+// The operators of the n angle subsets of a Joseph operator (subset j: the
+// angles j, j + n, ..., with the parent's geometry entries, so every row is
+// the parent's row bit for bit), built once per n and kept by the parent;
+// the row permutation that puts each subset's rows together (subset 0's
+// first) on the device.
+void joseph_make_subsets(tvs_op* op, int n) {
+    JosephGeom& g = op->joseph;
+    if (g.sub_n == n) return;
+    joseph_free_subsets(op);
+    std::vector<int> perm;
+    for (int j = 0; j < n; ++j) {
+        auto s = std::make_unique<tvs_op>();
+        s->ctx = op->ctx;
+        s->kind = OP_JOSEPH;
+        s->H = op->H;
+        s->W = op->W;
+        JosephGeom& sg = s->joseph;
+        sg.n_det = g.n_det;
+        sg.pixel = g.pixel;
+        sg.det_spacing = g.det_spacing;
+        g.sub_off.push_back((int)perm.size());
+        for (int a = j; a < g.n_ang; a += n) {
+            sg.host.push_back(g.host[a]);
+            perm.push_back(a);
+        }
+        sg.n_ang = (int)sg.host.size();
+        joseph_upload(s.get());
+        g.subsets.push_back(s.release());
+    }
+    g.sub_off.push_back((int)perm.size());
+    TVS_HIP(hipMalloc(&g.sub_perm, perm.size() * sizeof(int)));
+    TVS_HIP(hipMemcpy(g.sub_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+    g.sub_n = n;
+}
+
+void joseph_free_subsets(tvs_op* op) {
+    JosephGeom& g = op->joseph;
+    for (tvs_op* s : g.subsets) {
+        if (s->joseph.ang) hipFree(s->joseph.ang);
+        delete s;
+    }
+    g.subsets.clear();
+    g.sub_off.clear();
+    if (g.sub_perm) hipFree(g.sub_perm);
+    g.sub_perm = nullptr;
+    g.sub_n = 0;
+}
+
+}  // namespace tvs
+
+extern "C" tvs_status tvs_op_joseph_set_groups(tvs_op* op, int groups) {
+    return guarded([&] {
+        TVS_REQUIRE(op && op->kind == OP_JOSEPH, TVS_ERR_INVALID_ARG, "not a Joseph operator");
+        const int na = op->joseph.n_ang;
+        const int gmin = (na + joseph_rd_max_angles() - 1) / joseph_rd_max_angles();
+        TVS_REQUIRE(groups == 0 || (groups >= gmin && groups <= na), TVS_ERR_INVALID_ARG,
+                    "groups must be 0 (automatic) or in [ceil(n_ang / max angles per group), n_ang]");
+        use_device(op->ctx);
+        TVS_HIP(hipDeviceSynchronize());
+        graph_cache_clear(op->ctx);
+        op->joseph.rd_groups = groups;
+    });
+}
+
+extern "C" int tvs_op_joseph_groups(const tvs_op* op) {
+    if (!op || op->kind != OP_JOSEPH) return -1;
+    return joseph_rd_groups(op->ctx, op);
 }
 
 extern "C" void tvs_op_destroy(tvs_op* op) {
@@ -314,6 +402,7 @@ extern "C" void tvs_op_destroy(tvs_op* op) {
     if (op->blur.k_f) hipFree(op->blur.k_f);
     if (op->blur.k_d) hipFree(op->blur.k_d);
     if (op->joseph.ang) hipFree(op->joseph.ang);
+    joseph_free_subsets(op);
     delete op;
 }
 
@@ -572,6 +661,10 @@ extern "C" int tvs_coin(uint64_t seed, uint64_t stream_id, int64_t k, double p) 
     return tvs::coin(seed, stream_id, k, p);
 }
 
+extern "C" int tvs_subset(uint64_t seed, uint64_t stream_id, int64_t k, int n) {
+    return tvs::subset_draw(seed, stream_id, k, n);
+}
+
 // ================================================================ solvers
 namespace tvs {
 
@@ -813,7 +906,193 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
     });
 }
 
+// ------------------------------------------- stochastic angle subsets
+// SPDHG over the n angle subsets with the prox skipped as in PDHGSkip-2
+// (the paper's "Discussion and Future work"):
+//   w = x - sigma zbar;  xhat = w + sigma h;  theta: x+ = prox(w + coef h),
+//   h += (p/sigma)(x+ - xhat); else x+ = xhat;
+//   j = j_k:  y_j <- (y_j + tau (A_j x+ - b_j)) / (1 + tau);  dy = change;
+//   z += A_j^T dy;  zbar = z + n A_j^T dy;   z = zbar = A^T y at the start.
+// The sinogram is worked on in a row order that puts each subset's rows
+// together (b and y are permuted in and y back out), so that subset j is the
+// parent's rows [off_j, off_{j+1}) and its own operator's whole output.
+template <typename T>
+static void run_spdhg(tvs_op* op, int nsub, const T* b, const tvs_state* st, const tvs_params* P,
+                      const std::vector<uint8_t>& theta, const std::vector<int>& sub,
+                      double* obj_dev) {
+    tvs_ctx* ctx = op->ctx;
+    JosephGeom& g = op->joseph;
+    const int H = op->H, W = op->W, nd = g.n_det;
+    const size_t n = (size_t)H * W, m = op->out_size();
+    T* x = (T*)st->x;
+    T* h = (T*)st->h;
+    T* q = (T*)st->q;
+    T* y = (T*)st->y;
+    T* xhat = (T*)scratch(ctx, S_XHAT, n * sizeof(T));
+    T* v = (T*)scratch(ctx, S_V, n * sizeof(T));
+    const int xp_ld = W + 2 * JPAD, xTp_ld = H + 2 * JPAD;
+    T* xp = (T*)scratch(ctx, S_XBARP, (size_t)H * xp_ld * sizeof(T)) + JPAD;
+    T* xTp = (T*)scratch(ctx, S_XBARTP, (size_t)W * xTp_ld * sizeof(T)) + JPAD;
+    T* bp = (T*)scratch(ctx, S_SB, m * sizeof(T));
+    T* yp = (T*)scratch(ctx, S_SY, m * sizeof(T));
+    T* dy = (T*)scratch(ctx, S_SDY, m * sizeof(T));
+    T* z = (T*)scratch(ctx, S_SZ, n * sizeof(T));
+    T* zbar = (T*)scratch(ctx, S_SZB, n * sizeof(T));
+    launch_fill<T>(ctx, (size_t)H * xp_ld, T(0), xp - JPAD);
+    launch_fill<T>(ctx, (size_t)W * xTp_ld, T(0), xTp - JPAD);
+    launch_permute_rows<T>(ctx, g.n_ang, nd, g.sub_perm, b, bp, false);
+    launch_permute_rows<T>(ctx, g.n_ang, nd, g.sub_perm, y, yp, false);
+    launch_joseph_adj<T>(ctx, op, y, z, nullptr);
+    launch_copy<T>(ctx, n, z, zbar);
+    const double sigma = P->step, p = P->p;
+    const double lam = P->alpha * sigma / p;
+    const FgpConfig cfg = fgp_config(ctx, H, W, (int)sizeof(T));
+    PrimalStep<T> ps{};
+    ps.x = x;
+    ps.h = h;
+    ps.xhat = xhat;
+    ps.v = v;
+    ps.xbar = xp;
+    ps.xbarT = xTp;
+    ps.xbar_ld = xp_ld;
+    ps.xbarT_ld = xTp_ld;
+    ps.step = (T)sigma;
+    ps.coef = (T)(sigma - sigma / p);
+    ps.pdhg = 1;
+    ps.xcopy = 1;
+    ZAcc<T> za{z, zbar, (T)nsub};
+    const T tau = (T)P->dual_step;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        ps.theta = theta[kk];
+        launch_identity_adj_step<T>(ctx, H, W, zbar, ps);
+        if (ps.theta) {
+            T* qf = run_fgp<T>(ctx, H, W, v, lam, P->inner_iters, P->nonneg, q, cfg);
+            Finalize<T> f{};
+            f.v = v;
+            f.q = qf;
+            f.q_out = q;
+            f.x = x;
+            f.h = h;
+            f.xhat = xhat;
+            f.xbar = xp;
+            f.xbarT = xTp;
+            f.xbar_ld = xp_ld;
+            f.xbarT_ld = xTp_ld;
+            f.rate = (T)(p / sigma);
+            f.nonneg = P->nonneg;
+            f.mode = 3;
+            launch_finalize<T>(ctx, H, W, f);
+        }
+        const int j = sub[kk];
+        const tvs_op* sj = g.subsets[j];
+        const size_t off = (size_t)g.sub_off[j] * nd;
+        launch_joseph_fwd<T>(ctx, sj, xp, xTp, bp + off, yp + off, FWD_DUAL_PROX_DELTA, tau, dy);
+        launch_joseph_adj<T>(ctx, sj, dy, nullptr, nullptr, &za);
+        if (obj_dev) objective_dev<T>(op, b, x, P->alpha, obj_dev + kk);
+    }
+    launch_permute_rows<T>(ctx, g.n_ang, nd, g.sub_perm, yp, y, true);
+}
+
+template <typename T>
+static void prepare_spdhg(tvs_op* op, const tvs_params* P) {
+    tvs_ctx* ctx = op->ctx;
+    const JosephGeom& g = op->joseph;
+    const size_t n = (size_t)op->H * op->W, m = op->out_size();
+    scratch(ctx, S_XHAT, n * sizeof(T));
+    scratch(ctx, S_V, n * sizeof(T));
+    scratch(ctx, S_XBARP, (size_t)op->H * (op->W + 2 * JPAD) * sizeof(T));
+    scratch(ctx, S_XBARTP, (size_t)op->W * (op->H + 2 * JPAD) * sizeof(T));
+    for (Slot s : {S_SB, S_SY, S_SDY}) scratch(ctx, s, m * sizeof(T));
+    scratch(ctx, S_SZ, n * sizeof(T));
+    scratch(ctx, S_SZB, n * sizeof(T));
+    scratch(ctx, S_RES, m * sizeof(T));
+    scratch(ctx, S_Q1, 2 * n * sizeof(T));
+    scratch(ctx, S_Q2, 2 * n * sizeof(T));
+    scratch(ctx, S_Q3, 2 * n * sizeof(T));
+    beta_table_dev<T>(ctx, P->inner_iters + 1);
+    if (sizeof(T) == 4) {
+        size_t part = 0;
+        std::vector<const tvs_op*> ops(g.subsets.begin(), g.subsets.end());
+        ops.push_back(op);
+        for (const tvs_op* o : ops)
+            if (o->joseph.rd_ok) part = std::max(part, (size_t)joseph_rd_groups(ctx, o) * n * sizeof(T));
+        if (part) scratch(ctx, S_PARTIMG, part);
+    }
+}
+
+static tvs_status spdhg_solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* st,
+                              const tvs_params* P, int nsub, double* obj_trace,
+                              uint8_t* theta_trace, int32_t* subset_trace, tvs_report* report) {
+    return guarded([&] {
+        TVS_REQUIRE(op && b && st, TVS_ERR_INVALID_ARG, "null pointer");
+        TVS_REQUIRE(op->kind == OP_JOSEPH, TVS_ERR_UNSUPPORTED,
+                    "angle subsets need a Joseph (CT) operator");
+        check_dtype(dtype);
+        check_params(P, true);
+        TVS_REQUIRE(st->x && st->h && st->q && st->y, TVS_ERR_INVALID_ARG,
+                    "state x, h, q, y required");
+        TVS_REQUIRE(nsub >= 1 && nsub <= op->joseph.n_ang && nsub <= 1024, TVS_ERR_INVALID_ARG,
+                    "n_subsets must be in [1, min(n_ang, 1024)]");
+        tvs_ctx* ctx = op->ctx;
+        use_device(ctx);
+        const int64_t K = P->outer_iters;
+        std::vector<uint8_t> theta((size_t)K);
+        std::vector<int> sub((size_t)K);
+        int64_t nprox = 0;
+        for (int64_t kk = 0; kk < K; ++kk) {
+            theta[kk] = (uint8_t)coin(P->seed, P->stream_id, P->k0 + kk, P->p);
+            sub[kk] = subset_draw(P->seed, P->stream_id, P->k0 + kk, nsub);
+            nprox += theta[kk];
+        }
+        if (op->joseph.sub_n != nsub) {
+            TVS_HIP(hipDeviceSynchronize());
+            graph_cache_clear(ctx);
+            joseph_make_subsets(op, nsub);
+        }
+        double* obj_dev = nullptr;
+        if (obj_trace && K > 0) obj_dev = (double*)scratch(ctx, S_OBJ, (size_t)K * sizeof(double));
+        const bool use_graph = (P->flags & TVS_FLAG_GRAPH) && !obj_dev && K > 0;
+        if (dtype == TVS_F32)
+            prepare_spdhg<float>(op, P);
+        else
+            prepare_spdhg<double>(op, P);
+        auto enqueue = [&] {
+            if (dtype == TVS_F32)
+                run_spdhg<float>(op, nsub, (const float*)b, st, P, theta, sub, obj_dev);
+            else
+                run_spdhg<double>(op, nsub, (const double*)b, st, P, theta, sub, obj_dev);
+        };
+        if (use_graph) {
+            std::vector<uint64_t> key = graph_key(op, true, (int)dtype, b, st, P);
+            key.insert(key.end(), {0x5BD61ULL, (uint64_t)nsub});
+            graph_run_key(ctx, key, enqueue);
+        } else {
+            enqueue();
+        }
+        if (theta_trace && K > 0) std::memcpy(theta_trace, theta.data(), (size_t)K);
+        if (subset_trace)
+            for (int64_t kk = 0; kk < K; ++kk) subset_trace[kk] = sub[kk];
+        if (obj_dev) {
+            TVS_HIP(hipMemcpyAsync(obj_trace, obj_dev, (size_t)K * sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            TVS_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        if (report) {
+            report->n_prox = nprox;
+            report->iters = K;
+        }
+    });
+}
+
 }  // namespace tvs
+
+extern "C" tvs_status tvs_spdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                                    const tvs_params* params, int n_subsets, double* obj_trace,
+                                    uint8_t* theta_trace, int32_t* subset_trace,
+                                    tvs_report* report) {
+    return spdhg_solve(op, dtype, b, state, params, n_subsets, obj_trace, theta_trace,
+                       subset_trace, report);
+}
 
 extern "C" tvs_status tvs_proxskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
                                    const tvs_params* params, double* obj_trace,

@@ -114,6 +114,10 @@ void run_batched(tvs_ctx* ctx, int n, const tvs_slice* S, const T* b, T* x, T* h
     scratch(ctx, S_Q2, 2 * total * sizeof(T));
     scratch(ctx, S_Q3, 2 * total * sizeof(T));
     beta_table_dev<T>(ctx, P->inner_iters + 1);
+    // The tables are rewritten in place: wait until launches of an earlier
+    // call on this stream (which may still read them) have finished.  A copy
+    // from pageable memory is not ordered after work on a non-blocking stream.
+    TVS_HIP(hipStreamSynchronize(ctx->stream));
     TVS_HIP(hipMemcpy(d_sl, hs.data(), n * sizeof(BSlice<T>), hipMemcpyHostToDevice));
     TVS_HIP(hipMemcpy(d_pref, pl.pref_all.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
     if (!pl.ints.empty())

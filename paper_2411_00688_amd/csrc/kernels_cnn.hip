@@ -26,9 +26,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bf16, round to nearest even: the gfx950 conversion instruction
-// (v_cvt_pk_bf16_f32).  For finite inputs (denormals included) it equals the
-// integer rounding of the bit pattern, (u + 0x7FFF + lsb) >> 16, which the
-// oracle uses; the forward and gradient parity tests compare the two.
+// (v_cvt_pk_bf16_f32).  For finite inputs (denormals included) round to
+// nearest even is the integer rounding of the bit pattern,
+// (u + 0x7FFF + lsb) >> 16.  The parity tests compare the network against
+// the float64 oracle within the bounds BF16 operands allow.
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));

@@ -825,15 +825,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
             f.z[g] = z;
         } else {
             f.h[g] = hh[p] + f.rate * (z - xh[p]);
-            if (f.mode == 2) {
-                const T xb = T(2) * z - xo[p];
+            if (f.mode >= 2) {
+                // PDHGSkip-2 extrapolates; the stochastic-angle method
+                // (mode 3) takes x+ itself
+                const T xb = f.mode == 3 ? z : T(2) * z - xo[p];
                 f.xbar[(size_t)i * f.xbar_ld + j] = xb;
                 s_t[li][lj] = xb;
             }
             f.x[g] = z;
         }
     }
-    if (f.mode == 2 && f.xbarT) {
+    if (f.mode >= 2 && f.xbarT) {
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < 4; ++p) {

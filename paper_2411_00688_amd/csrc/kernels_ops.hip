@@ -32,11 +32,19 @@ __device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, int 
     }
     ps.x[g] = xh;
     if (ps.pdhg) {
-        const T xb = T(2) * xh - x;
+        const T xb = ps.xcopy ? xh : T(2) * xh - x;
         ps.xbar[(size_t)i * ps.xbar_ld + j] = xb;
         return xb;
     }
     return T(0);
+}
+
+// z += s; zbar = z + nsub s (the stochastic-angle method's dual sums).
+template <typename T>
+__device__ __forceinline__ void z_accumulate(const ZAcc<T>& za, size_t g, T s) {
+    const T zn = za.z[g] + s;
+    za.z[g] = zn;
+    za.zbar[g] = zn + za.nsub * s;
 }
 
 // Splits the 32.32 fixed-point coordinate U (an integer-valued double with
@@ -109,6 +117,29 @@ __global__ __launch_bounds__(256) void transpose_kernel(int H, int W, const T* x
         const int jj = idx / 32, ii = idx % 32;
         if (i0 + ii < H && j0 + jj < W) xT[(size_t)(j0 + jj) * H + i0 + ii] = t[ii][jj];
     }
+}
+
+// Row permutation of a rows x cols array: gather dst[r] = src[perm[r]], or
+// scatter dst[perm[r]] = src[r].
+template <typename T>
+__global__ __launch_bounds__(256) void permute_rows_kernel(int rows, int cols, const int* perm,
+                                                           const T* src, T* dst, int scatter) {
+    const int r = (int)blockIdx.y;
+    const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (r >= rows || c >= cols) return;
+    const size_t pr = (size_t)perm[r];
+    if (scatter)
+        dst[pr * cols + c] = src[(size_t)r * cols + c];
+    else
+        dst[(size_t)r * cols + c] = src[pr * cols + c];
+}
+
+template <typename T>
+void launch_permute_rows(tvs_ctx* ctx, int rows, int cols, const int* perm, const T* src, T* dst,
+                         bool scatter) {
+    hipLaunchKernelGGL((permute_rows_kernel<T>), dim3(div_up(cols, 256), rows), dim3(256), 0,
+                       ctx->stream, rows, cols, perm, src, dst, scatter ? 1 : 0);
+    TVS_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -377,11 +408,27 @@ struct JFwdArgs {
     int x_ld, xT_ld;
     const T* b;
     T* y;
+    T* dy;      // FWD_DUAL_PROX_DELTA: y_new - y_old
     int H, W, n_det;
     int epi;
     int small;  // both padded copies span less than 4 GiB
     T tau;
 };
+
+template <typename T>
+__device__ __forceinline__ void fwd_epilogue(int epi, size_t o, T s, const T* b, T* y, T* dy,
+                                             T tau) {
+    if (epi == FWD_STORE) {
+        y[o] = s;
+    } else if (epi == FWD_RESIDUAL) {
+        y[o] = s - b[o];
+    } else {
+        const T yo = y[o];
+        const T yn = (yo + tau * (s - b[o])) / (T(1) + tau);
+        y[o] = yn;
+        if (epi == FWD_DUAL_PROX_DELTA) dy[o] = yn - yo;
+    }
+}
 
 // Block: 64 adjacent bins of one angle (lane = bin) x SEG wavefronts, each
 // summing a contiguous part of the step range; the partial sums are added in
@@ -501,19 +548,13 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
         for (int k = 1; k < SEG; ++k) s += part[k][lane];
         s *= (T)g.wgt;
         const size_t o = (size_t)blockIdx.y * a.n_det + d;
-        if (a.epi == FWD_STORE) {
-            a.y[o] = s;
-        } else if (a.epi == FWD_RESIDUAL) {
-            a.y[o] = s - a.b[o];
-        } else {
-            a.y[o] = (a.y[o] + a.tau * (s - a.b[o])) / (T(1) + a.tau);
-        }
+        fwd_epilogue<T>(a.epi, o, s, a.b, a.y, a.dy, a.tau);
     }
 }
 
 template <typename T>
 void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b, T* y,
-                       int epi, T tau) {
+                       int epi, T tau, T* dy) {
     JFwdArgs<T> a;
     a.ang = op->joseph.ang;
     a.x = x;
@@ -522,6 +563,7 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.xT_ld = op->H + 2 * JPAD;
     a.b = b;
     a.y = y;
+    a.dy = dy;
     a.H = op->H;
     a.W = op->W;
     a.n_det = op->joseph.n_det;
@@ -597,6 +639,8 @@ struct JAdjArgs {
     T* x_out;
     PrimalStep<T> ps;
     int has_ps;
+    ZAcc<T> za;
+    int has_za;
 };
 
 // One angle of the backprojector for the thread's 4 pixels, with NC
@@ -733,6 +777,8 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
             const size_t gidx = (size_t)i * a.W + j;
             if (a.has_ps)
                 s_t[li][lj] = primal_step(a.ps, gidx, i, j, acc[r]);
+            else if (a.has_za)
+                z_accumulate(a.za, gidx, acc[r]);
             else
                 a.x_out[gidx] = acc[r];
         }
@@ -752,8 +798,9 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(JAdjArgs<T> a) {
 // Ray-driven backprojector for float32 data and detector spacing >= pixel
 // (|Aq| >= 2^32: at one step two rays never floor to the same pixel).
 //
-// Block: a 52 x 52 pixel tile and one group of angles (g, g + G, ...), four
-// wavefronts.  For a row-stepping angle wavefront w owns tile rows
+// Block: a 52 x 52 pixel tile and one group of angles (g, g + G, ...),
+// RD_H sets of four wavefronts, set h taking the group's angles h, h + RD_H,
+// ...  For a row-stepping angle wavefront w owns tile rows
 // 13 w .. 13 w + 12, for a column-stepping angle the same columns.  Per
 // (wavefront, angle) the 64 lanes take 64 consecutive rays that include every
 // ray reaching the wavefront's strip; a lane keeps its ray, its sinogram value
@@ -770,9 +817,8 @@ static constexpr int RD_P = 52;     // tile side
 static constexpr int RD_L = 13;     // steps (rows or columns) per wavefront
 static constexpr int RD_NB = 128;   // staged bins per angle
 static constexpr int RD_MAXA = 36;  // at most this many angles per group
-static constexpr int RD_H = 2;      // wavefront sets per tile, set h taking angles h, h + 2, ...
+static constexpr int RD_H = 2;      // wavefront sets per tile, set h taking angles h, h + RD_H, ...
 static constexpr int RD_T = 64 * 4 * RD_H;  // threads per block
-static_assert(RD_H == 2, "the two sets' sums are combined in pairs");
 static_assert(4 * RD_L == RD_P, "four wavefronts cover the tile");
 static_assert(RD_P + 1 < 62, "the lanes past the strip (RD_P, RD_P + 1, 62, 63) are no pixel lanes");
 
@@ -958,9 +1004,10 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
     rd_class<0>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
     rd_class<1>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
     // Column-stepping sums are held per (column = 13 w + k, row = lane) and
-    // are transposed through tileT.  Set 1 stores both its sums, set 0 adds
-    // its column sums in place and writes the tile: a fixed order per pixel.
-    if (hf == 1 && lane < RD_P) {
+    // are transposed through tileT.  The last set stores both its sums, the
+    // sets before it add theirs in place in descending order, and set 0 adds
+    // its column sums and writes the tile: a fixed order per pixel.
+    if (hf == RD_H - 1 && lane < RD_P) {
 #pragma unroll
         for (int k = 0; k < RD_L; ++k) {
             tileT[lane][RD_L * w + k] = accC[k];
@@ -968,6 +1015,17 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
         }
     }
     __syncthreads();
+#pragma unroll
+    for (int hs = RD_H - 2; hs >= 1; --hs) {
+        if (hf == hs && lane < RD_P) {
+#pragma unroll
+            for (int k = 0; k < RD_L; ++k) {
+                tileT[lane][RD_L * w + k] += accC[k];
+                rowS[RD_L * w + k][lane] += accR[k];
+            }
+        }
+        __syncthreads();
+    }
     if (hf == 0 && lane < RD_P) {
 #pragma unroll
         for (int k = 0; k < RD_L; ++k) tileT[lane][RD_L * w + k] += accC[k];
@@ -988,7 +1046,8 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
 // (store, or the data step with the transposed xbar copy).  32 x 32 tiles.
 template <typename T>
 __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int G, int H, int W,
-                                                              T* x_out, PrimalStep<T> ps, int has_ps) {
+                                                              T* x_out, PrimalStep<T> ps, int has_ps,
+                                                              ZAcc<T> za, int has_za) {
     // one thread per pixel of a 32 x 32 tile: 16 waves per block keep the
     // G independent partial loads of many pixels in flight
     __shared__ T s_t[32][33];
@@ -1012,6 +1071,8 @@ __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int
         }
         if (has_ps)
             s_t[li][lj] = primal_step(ps, gi, i, j, s);
+        else if (has_za)
+            z_accumulate(za, gi, s);
         else
             x_out[gi] = s;
     }
@@ -1019,8 +1080,10 @@ __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int
         store_tile_transposed<T, 1024>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
 }
 
+int joseph_rd_max_angles() { return RD_MAXA; }
+
 // Angle groups of the ray-driven backprojector (one block per tile and
-// group), chosen once per operator.
+// group), chosen once per operator unless set by tvs_op_joseph_set_groups.
 int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op) {
     const JosephGeom& jg = op->joseph;
     if (jg.rd_groups > 0) return jg.rd_groups;
@@ -1048,7 +1111,7 @@ int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op) {
 
 template <typename T>
 void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
-                       const PrimalStep<T>* ps) {
+                       const PrimalStep<T>* ps, const ZAcc<T>* za) {
     JAdjArgs<T> a{};
     a.ang = op->joseph.ang;
     a.n_ang = op->joseph.n_ang;
@@ -1060,6 +1123,9 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     if (ps) {
         a.ps = *ps;
         a.has_ps = 1;
+    } else if (za) {
+        a.za = *za;
+        a.has_za = 1;
     }
     if constexpr (sizeof(T) == 4) {
         if (op->joseph.rd_ok) {
@@ -1080,7 +1146,7 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
             TVS_LAUNCH_CHECK();
             hipLaunchKernelGGL((joseph_adj_sum_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)),
                                dim3(1024), 0, ctx->stream, (const T*)part, G, a.H, a.W, x_out, a.ps,
-                               a.has_ps);
+                               a.has_ps, a.za, a.has_za);
             TVS_LAUNCH_CHECK();
             return;
         }
@@ -1095,17 +1161,19 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     template void launch_copy<T>(tvs_ctx*, size_t, const T*, T*);                                \
     template void launch_fill<T>(tvs_ctx*, size_t, T, T*);                                       \
     template void launch_transpose<T>(tvs_ctx*, int, int, const T*, T*);                         \
+    template void launch_permute_rows<T>(tvs_ctx*, int, int, const int*, const T*, T*, bool);    \
     template void launch_identity_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&);   \
     template void launch_identity_adj_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&); \
     template void launch_dual_prox_pointwise<T>(tvs_ctx*, size_t, const T*, const T*, T*, T);    \
     template void launch_blur<T>(tvs_ctx*, const tvs_op*, bool, const T*, const T*, T*);         \
     template void launch_blur_dual_prox<T>(tvs_ctx*, const tvs_op*, const T*, const T*, T*, T);  \
     template void launch_blur_adjoint_step<T>(tvs_ctx*, const tvs_op*, const T*, const PrimalStep<T>&); \
-    template void launch_joseph_fwd<T>(tvs_ctx*, const tvs_op*, const T*, const T*, const T*, T*, int, T); \
+    template void launch_joseph_fwd<T>(tvs_ctx*, const tvs_op*, const T*, const T*, const T*, T*, int, T, T*); \
     template void launch_pad_copy<T>(tvs_ctx*, int, int, const T*, T*, T*);                      \
     template void launch_identity_step_batched<T>(tvs_ctx*, const BSlice<T>*, const int*, int, int, \
                                                   const uint8_t*, const T*, T*, const T*, T*, T*, T); \
-    template void launch_joseph_adj<T>(tvs_ctx*, const tvs_op*, const T*, T*, const PrimalStep<T>*);
+    template void launch_joseph_adj<T>(tvs_ctx*, const tvs_op*, const T*, T*, const PrimalStep<T>*, \
+                                       const ZAcc<T>*);
 TVS_INST(float)
 TVS_INST(double)
 #undef TVS_INST

@@ -51,7 +51,8 @@ struct Scratch {
 enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
     S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
-    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_QNET, S_SEL, S_COUNT
+    S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_QNET, S_SEL,
+    S_SB, S_SY, S_SDY, S_SZ, S_SZB, S_COUNT
 };
 
 struct GraphEntry;
@@ -136,6 +137,13 @@ struct JosephGeom {
     bool rd_ok = false;
     // angle groups of the ray-driven backprojector, chosen on first use
     mutable int rd_groups = 0;
+    // angle-subset operators of the stochastic-angle method (sub_n of them,
+    // owned), each subset's first row in the permuted sinogram, and the
+    // permutation (permuted row -> angle) on the device
+    int sub_n = 0;
+    std::vector<tvs_op*> subsets;
+    std::vector<int> sub_off;
+    int* sub_perm = nullptr;
 };
 
 struct BlurGeom {
@@ -188,6 +196,16 @@ struct PrimalStep {
     T step, coef;
     int theta;
     int pdhg;
+    int xcopy;     // pdhg and xcopy: the padded copies take xhat itself (no extrapolation)
+};
+
+// Backprojector epilogue of the stochastic-angle method: s = A_j^T dy;
+// z += s; zbar = z + nsub s.
+template <typename T>
+struct ZAcc {
+    T* z;
+    T* zbar;
+    T nsub;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -226,7 +244,7 @@ struct Finalize {
     int xbar_ld, xbarT_ld;
     T rate;
     int nonneg;
-    int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip
+    int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip, 3: stochastic angles (xbar = z)
 };
 template <typename T> void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f);
 
@@ -244,6 +262,9 @@ template <typename T>
 void launch_axpby(tvs_ctx* ctx, size_t n, T a, const T* x, T bcoef, const T* y, T* out);
 template <typename T> void launch_copy(tvs_ctx* ctx, size_t n, const T* x, T* y);
 template <typename T> void launch_fill(tvs_ctx* ctx, size_t n, T val, T* y);
+template <typename T>
+void launch_permute_rows(tvs_ctx* ctx, int rows, int cols, const int* perm, const T* src, T* dst,
+                         bool scatter);
 template <typename T> void launch_transpose(tvs_ctx* ctx, int H, int W, const T* x, T* xT);
 
 // Blur: out = A x (- b if b), or A^T y followed by a PrimalStep.
@@ -261,18 +282,23 @@ void launch_blur_adjoint_step(tvs_ctx* ctx, const tvs_op* op, const T* r, const 
 // so that samples falling just outside the image read zeros instead of
 // being masked; x and xT point at element (0, 0) of each copy.
 constexpr int JPAD = 4;
-enum FwdEpi { FWD_STORE = 0, FWD_RESIDUAL = 1, FWD_DUAL_PROX = 2 };
+enum FwdEpi { FWD_STORE = 0, FWD_RESIDUAL = 1, FWD_DUAL_PROX = 2, FWD_DUAL_PROX_DELTA = 3 };
+// FWD_DUAL_PROX_DELTA: the dual prox of FWD_DUAL_PROX, and dy = y_new - y_old.
 template <typename T>
 void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b,
-                       T* y, int epi, T tau);
+                       T* y, int epi, T tau, T* dy = nullptr);
 // Writes both padded copies of the H x W image x (pads included).
 template <typename T>
 void launch_pad_copy(tvs_ctx* ctx, int H, int W, const T* x, T* xp, T* xTp);
 int joseph_rd_groups(const tvs_ctx* ctx, const tvs_op* op);
+int joseph_rd_max_angles();
+void joseph_upload(tvs_op* op);
+void joseph_make_subsets(tvs_op* op, int n);
+void joseph_free_subsets(tvs_op* op);
 bool joseph_rd_angle_ok(const JAngle& e);
 template <typename T>
 void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
-                       const PrimalStep<T>* ps);
+                       const PrimalStep<T>* ps, const ZAcc<T>* za = nullptr);
 
 // Reductions (deterministic two-stage, float64 accumulation).  Each returns
 // a device pointer to one double holding the result.
@@ -294,6 +320,7 @@ void launch_combine(tvs_ctx* ctx, const double* x, double a, const double* y, do
 // host helpers
 uint64_t splitmix_mix(uint64_t z);
 int coin(uint64_t seed, uint64_t stream, int64_t k, double p);
+int subset_draw(uint64_t seed, uint64_t stream, int64_t k, int n);
 const double* beta_table_host(int n);
 
 template <typename T> const T* beta_table_dev(tvs_ctx* ctx, int n);

@@ -51,6 +51,18 @@ def test_coin_bitwise_equals_oracle():
     assert T.tvs_coin(1, 2, -1, 0.5) == -1
 
 
+def test_subset_draw_bitwise_equals_oracle():
+    rng = np.random.default_rng(1)
+    for _ in range(100):
+        seed = int(rng.integers(0, 2**63))
+        stream = int(rng.integers(0, 2**20))
+        n = int(rng.choice([1, 2, 3, 7, 10, 18, 180, 1024]))
+        for k in list(range(0, 40)) + [10**6, 2**40]:
+            assert T.tvs_subset(seed, stream, k, n) == O.subset(seed, stream, k, n)
+    assert T.tvs_subset(1, 2, 0, 0) == -1 and T.tvs_subset(1, 2, -1, 4) == -1
+    assert T.tvs_subset(1, 2, 0, 1025) == -1
+
+
 def test_null_arguments_are_rejected_without_a_device():
     L = _lib.lib()
     out = C.c_void_p()
@@ -58,6 +70,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"null context" in L.tvs_last_error()
     assert L.tvs_tv_prox(None, 0, 4, 4, None, 0.1, 1, 0, None, None, None) == 1
     assert L.tvs_proxskip(None, 0, None, None, None, None, None, None) == 1
+    assert L.tvs_spdhgskip(None, 0, None, None, None, 4, None, None, None, None) == 1
     assert L.tvs_fgp_set_variant(None, 0, 4, 4, 0) == 1
     # variant table is host data
     n = T.tvs_fgp_variant_count()

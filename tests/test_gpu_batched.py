@@ -74,6 +74,50 @@ def test_batched_equals_single_slice_solves(ctx, dt):
             T.tvs_op_destroy(op)
 
 
+def single_solve(ctx, sl, bb, dt, K, Kin):
+    H, W = sl["H"], sl["W"]
+    op = T.tvs_op_identity(ctx, H, W)
+    try:
+        xs = torch.zeros(H, W, dtype=dt, device="cuda")
+        hs = torch.zeros_like(xs)
+        qs = torch.zeros(2, H, W, dtype=dt, device="cuda")
+        r = T.tvs_proxskip(op, torch.tensor(bb, dtype=dt, device="cuda"), xs, hs, qs,
+                           sl["alpha"], 1.0, sl["p"], K, Kin, seed=sl["seed"],
+                           stream_id=sl["stream_id"])
+        return r["n_prox"], xs, hs, qs
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_batched_back_to_back_on_side_stream(ctx):
+    """Two batched calls with different plans (slice tables, work lists, coin
+    plans) enqueued back to back on a non-blocking torch stream, with no host
+    wait between them: the second call rewrites the context's tables, which
+    must not change what the first call's launches read."""
+    side = torch.cuda.Stream()
+    c2 = T.tvs_ctx_create(0, stream=side)
+    runs = []
+    try:
+        with torch.cuda.stream(side):
+            for sizes, seed0, K, Kin in ((SIZES, 50, 30, 10),
+                                         ([(70, 90), (16, 16), (128, 40)], 80, 24, 7)):
+                slices, bs, total = make_batch(sizes, F32, seed0=seed0)
+                b, x, h, q = pools(bs, slices, total, F32)
+                nprox = T.tvs_proxskip_batched(c2, slices, b, x, h, q, 1.0, K, Kin)
+                runs.append((slices, bs, x, h, q, nprox, K, Kin))
+        side.synchronize()
+        for slices, bs, x, h, q, nprox, K, Kin in runs:
+            for sl, bb, npx in zip(slices, bs, nprox):
+                n_s, xs, hs, qs = single_solve(ctx, sl, bb, F32, K, Kin)
+                assert n_s == npx
+                assert torch.equal(slice_of(x, sl), xs)
+                assert torch.equal(slice_of(h, sl), hs)
+                assert torch.equal(slice_of(q, sl, 2), qs)
+    finally:
+        torch.cuda.synchronize()
+        T.tvs_ctx_destroy(c2)
+
+
 @pytest.mark.parametrize("dt", [F64, F32])
 def test_batched_strip_variant_equals_tile_variant(ctx, dt):
     """Slices wider than one 256-column strip (halo columns between strips,

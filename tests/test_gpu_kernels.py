@@ -294,6 +294,51 @@ def test_joseph_gpu_exact_transpose(ctx, gi):
         T.tvs_op_destroy(op)
 
 
+@pytest.mark.parametrize("H,W,na,nd,px,ds", [(64, 64, 45, 93, 2 / 64, 2 / 64),
+                                              (100, 90, 30, 140, 0.02, 0.025),
+                                              (24, 28, 20, 41, 0.1, 0.1)])
+def test_joseph_rd_groups(ctx, H, W, na, nd, px, ds):
+    """The float32 ray-driven backprojector with the angle-group count forced
+    (several angles per group, groups of uneven size, every wavefront set
+    busy, one group): against the oracle, and the dense matrices of A and
+    A^T transposes bit for bit on the small geometry."""
+    ang = synth.parallel_beam_angles(na)
+    A = O.joseph(H, W, ang, nd, px, ds)
+    r = rng(13)
+    y = as_input(r.standard_normal((na, nd)), F32)
+    op = T.tvs_op_ct_joseph(ctx, H, W, ang, nd, px, ds)
+    try:
+        auto = T.tvs_op_joseph_groups(op)
+        assert 1 <= auto <= na
+        gmin = -(-na // 36)   # at most 36 angles per group
+        for G in sorted({gmin, 3, 4, 7, na} & set(range(gmin, na + 1))):
+            T.tvs_op_joseph_set_groups(op, G)
+            assert T.tvs_op_joseph_groups(op) == G
+            back = torch.empty(H, W, dtype=F32, device="cuda")
+            T.tvs_op_adjoint(op, dev(y, F32), back)
+            assert rel_l2(host(back), A.adjoint(y)) < 2e-6, G
+            if H * W <= 1024:
+                M = _dense_gpu(lambda a, b: T.tvs_op_apply(op, a, b), H * W, (H, W), (na, nd), F32)
+                MT = _dense_gpu(lambda a, b: T.tvs_op_adjoint(op, a, b), na * nd, (na, nd),
+                                (H, W), F32)
+                assert np.array_equal(MT, M.T), G
+        with pytest.raises(T.TvsError):
+            T.tvs_op_joseph_set_groups(op, na + 1)
+        with pytest.raises(T.TvsError):
+            T.tvs_op_joseph_set_groups(op, gmin - 1 if gmin > 1 else -1)
+        T.tvs_op_joseph_set_groups(op, 0)
+        assert T.tvs_op_joseph_groups(op) == auto
+    finally:
+        T.tvs_op_destroy(op)
+    idop = T.tvs_op_identity(ctx, 8, 8)
+    try:
+        with pytest.raises(T.TvsError):
+            T.tvs_op_joseph_set_groups(idop, 1)
+        assert T.tvs_op_joseph_groups(idop) == -1
+    finally:
+        T.tvs_op_destroy(idop)
+
+
 def test_joseph_full_size(ctx):
     """The 512^2, 180-angle, 725-bin CT operator: float32 projector and
     backprojector against the oracle, and the float64 adjoint identity."""
@@ -309,9 +354,16 @@ def test_joseph_full_size(ctx):
         T.tvs_op_apply(op, dev(ui, F32), y)
         assert rel_l2(host(y), A.apply(ui)) < 2e-6
         yi = as_input(eta, F32)
+        ref = A.adjoint(yi)
         back = torch.empty(N, N, dtype=F32, device="cuda")
         T.tvs_op_adjoint(op, dev(yi, F32), back)
-        assert rel_l2(host(back), A.adjoint(yi)) < 2e-6
+        assert rel_l2(host(back), ref) < 2e-6
+        # forced group counts: 36 angles per group (5), uneven groups (7)
+        for G in (5, 7):
+            T.tvs_op_joseph_set_groups(op, G)
+            T.tvs_op_adjoint(op, dev(yi, F32), back)
+            assert rel_l2(host(back), ref) < 2e-6, G
+        T.tvs_op_joseph_set_groups(op, 0)
         x = torch.tensor(u, device="cuda")
         yy = torch.tensor(eta, device="cuda")
         ax = torch.empty(na, nd, dtype=F64, device="cuda")
