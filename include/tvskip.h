@@ -145,6 +145,25 @@ tvs_status tvs_tv_prox(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* 
                        double lambda, int inner_iters, int nonneg, void* q_inout,
                        void* z_out, double* rel_gap_out);
 
+/* The TV prox of tvs_tv_prox (same kernels, same results bit for bit) for
+ * callers that cannot allocate device memory: code under HIP stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It allocates
+ * nothing: its work buffers (the momentum table and three dual fields) live
+ * in one static device array of TVS_NOALLOC_SCRATCH_BYTES per device, held
+ * until the process ends, whose device address the context creation looks
+ * up.  Requires 256-byte-aligned (inner_iters + 1) + 3 * (2 H W) elements of
+ * dtype to fit (float32: about 1.39 million pixels, e.g. 1024 x 1024;
+ * float64 about 0.69 million, e.g. 800 x 800); larger sizes return
+ * TVS_ERR_INVALID_ARG before anything is enqueued.  No rel_gap output (that
+ * would need a reduction buffer and a host wait).  Every call on a device
+ * shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race; calls in one stream are ordered.  Arguments
+ * as tvs_tv_prox; enqueues on the context's stream and does not wait. */
+#define TVS_NOALLOC_SCRATCH_BYTES (32u << 20)
+tvs_status tvs_tv_prox_noalloc(tvs_ctx* ctx, tvs_dtype dtype, int H, int W, const void* v,
+                               double lambda, int inner_iters, int nonneg, void* q_inout,
+                               void* z_out);
+
 /* Duality gap of the TV prox at dual point q: with z = P_X(v + div q),
  *   gap = sum_i lambda |(D z)_i| - <(D z)_i, q_i>,  P(z) = 1/2|z - v|^2 + lambda TV(z).
  * Host outputs (nullable); synchronises. */

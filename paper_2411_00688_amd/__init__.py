@@ -22,7 +22,8 @@ __all__ = [
     "tvs_op_identity", "tvs_op_blur_periodic", "tvs_op_ct_joseph", "tvs_op_destroy",
     "tvs_op_out_size", "tvs_op_apply", "tvs_op_adjoint", "tvs_op_norm",
     "tvs_op_joseph_set_groups", "tvs_op_joseph_groups",
-    "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_gap", "tvs_objective", "tvs_coin",
+    "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_prox_noalloc", "tvs_tv_gap", "tvs_objective",
+    "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
     "tvs_spdhgskip", "tvs_subset",
     "tvs_dual_rof_proxskip",
@@ -183,6 +184,17 @@ def tvs_tv_prox(ctx: int, v, lam: float, inner_iters: int, nonneg: int, q, z,
                             int(nonneg), _ptr(q, 2 * H * W, d), _ptr(z, H * W, d),
                             C.byref(g) if want_gap else None))
     return g.value if want_gap else None
+
+
+def tvs_tv_prox_noalloc(ctx: int, v, lam: float, inner_iters: int, nonneg: int, q, z):
+    """tvs_tv_prox on the library's static device array (allocates nothing;
+    calls overlapping on one device race).  q is the warm dual in and the
+    final dual out."""
+    H, W = v.shape
+    d = _dtype_code(v)
+    check(lib().tvs_tv_prox_noalloc(C.c_void_p(ctx), d, H, W, _ptr(v), float(lam),
+                                    int(inner_iters), int(nonneg), _ptr(q, 2 * H * W, d),
+                                    _ptr(z, H * W, d)))
 
 
 def tvs_tv_gap(ctx: int, v, lam: float, nonneg: int, q):

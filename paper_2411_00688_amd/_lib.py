@@ -90,6 +90,8 @@ PROTOTYPES = {
     "tvs_div": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp]),
     "tvs_tv_prox": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_double, C.c_int, C.c_int,
                               vp, vp, dp]),
+    "tvs_tv_prox_noalloc": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_double, C.c_int,
+                                      C.c_int, vp, vp]),
     "tvs_tv_gap": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_double, C.c_int, vp, dp, dp]),
     "tvs_objective": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp]),
     "tvs_coin": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_double]),

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtvskip.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "graph.hip", "tune.hip", "batched.hip", "cnn.hip", "light_prox.hip",
+SOURCES = ["api.hip", "graph.hip", "tune.hip", "batched.hip", "cnn.hip", "light_prox.hip", "noalloc.hip",
            "kernels_fgp.hip",
            "kernels_ops.hip", "kernels_reduce.hip", "kernels_cnn.hip"]
 

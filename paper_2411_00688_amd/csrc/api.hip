@@ -172,6 +172,12 @@ extern "C" tvs_status tvs_ctx_create(int device, void* hip_stream, tvs_ctx** out
         c->stream = (hipStream_t)hip_stream;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+        try {
+            noalloc_setup(device);  // device address of the no-allocation scratch
+        } catch (...) {
+            delete c;
+            throw;
+        }
         *out = c;
     });
 }

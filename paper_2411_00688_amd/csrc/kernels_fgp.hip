@@ -650,12 +650,23 @@ template <typename T>
 T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
            T* q_inout, const FgpConfig& cfg, const int* run_flag) {
     const size_t plane = (size_t)H * W;
-    const int vi = find_variant(cfg, (int)sizeof(T));
-    const int TS = kFgpVariants[vi].ts;
-    T* bufs[4] = {q_inout, (T*)scratch(ctx, S_Q1, 2 * plane * sizeof(T)),
+    T* work[3] = {(T*)scratch(ctx, S_Q1, 2 * plane * sizeof(T)),
                   (T*)scratch(ctx, S_Q2, 2 * plane * sizeof(T)),
                   (T*)scratch(ctx, S_Q3, 2 * plane * sizeof(T))};
     const T* beta = beta_table_dev<T>(ctx, iters + 1);
+    return run_fgp_bufs<T>(ctx, H, W, v, lambda, iters, nonneg, q_inout, work, beta, cfg, run_flag);
+}
+
+// The FGP launch sequence on caller-given work buffers (three dual fields of
+// 2 H W elements) and momentum table (iters + 1 entries).
+template <typename T>
+T* run_fgp_bufs(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
+                T* q_inout, T* const* work, const T* beta, const FgpConfig& cfg,
+                const int* run_flag) {
+    const size_t plane = (size_t)H * W;
+    const int vi = find_variant(cfg, (int)sizeof(T));
+    const int TS = kFgpVariants[vi].ts;
+    T* bufs[4] = {q_inout, work[0], work[1], work[2]};
     T* qa = q_inout;
     T* qb = q_inout;  // iteration 0 forms r = q_warm whatever beta is
     int k = 0;
@@ -968,6 +979,8 @@ void launch_div(tvs_ctx* ctx, int H, int W, const T* q, T* u) {
 #define TVS_INST(T)                                                                          \
     template T* run_fgp<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, const FgpConfig&,  \
                            const int*);                                                         \
+    template T* run_fgp_bufs<T>(tvs_ctx*, int, int, const T*, double, int, int, T*, T* const*,    \
+                                const T*, const FgpConfig&, const int*);                        \
     template T* run_fgp_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&, const T*, T*,   \
                                    size_t, int, int, const FgpConfig&);                          \
     template void launch_finalize_batched<T>(tvs_ctx*, const BSlice<T>*, const BatchLists&,      \

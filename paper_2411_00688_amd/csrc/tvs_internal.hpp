@@ -228,6 +228,16 @@ FgpConfig fgp_variant(int index);
 template <typename T>
 T* run_fgp(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
            T* q_inout, const FgpConfig& cfg, const int* run_flag = nullptr);
+// The same on caller-given work buffers (three fields of 2 H W elements) and
+// momentum table (iters + 1 entries); allocates nothing.
+template <typename T>
+T* run_fgp_bufs(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
+                T* q_inout, T* const* work, const T* beta, const FgpConfig& cfg,
+                const int* run_flag = nullptr);
+// The allocation-free prox's static device array: its device address on
+// `device` (looked up once per device, with the device current).
+void noalloc_setup(int device);
+void* noalloc_ptr(int device);
 
 // z = P_X(v + div q) and the ProxSkip / PDHGSkip bookkeeping after a prox.
 template <typename T>
