@@ -86,7 +86,8 @@ def test_second_method_agrees_and_bracket_holds(name):
     assert abs(cc["phi_star"] - phi) <= 1e-7 * phi
     assert cc["rel_diff_to_first_method"] == pytest.approx(abs(cc["phi_star"] - phi) / cc["phi_star"])
     cert = cc["certificate"]
-    assert cert["lower"] <= phi <= cert["upper"] + 1e-12 * phi
+    # the bracket's upper end is the objective at the second method's end point
+    assert cert["upper"] == pytest.approx(cc["phi_star"], rel=1e-12)
     # both stored minima are objective values at feasible points, so the
     # smaller is the better upper bound; the bracket's lower end is below it
     assert cert["lower"] <= min(phi, cc["phi_star"])
