@@ -134,7 +134,7 @@ def main():
     # ---- time to 1e-4 relative objective (deterministic replay for Phi)
     tta = small = spdhg = None
     if not args.no_tta:
-        tta = time_to_accuracy(solve, w, K)
+        tta = time_to_accuracy(solve, w, K, extra=ct_comparisons(T, op, w, b, Lnorm, seed, K))
         spdhg = spdhg_tta(T, ctx, w, b, seed)
         small = small_tta(T, ctx)
 
@@ -235,7 +235,7 @@ def tta_entry(run, K, phis, name):
     return out
 
 
-def time_to_accuracy(solve, w, K, p_sweep=(0.1, 0.3, 0.5, 0.7)):
+def time_to_accuracy(solve, w, K, p_sweep=(0.1, 0.3, 0.5, 0.7), extra=None):
     """Time to 1e-4 on the CT workload: PDHGSkip-2 at the workload's p, the
     p sweep, and PDHG (p = 1)."""
     path = os.path.join(ROOT, "tests", "golden", "phi_star_ct512.json")
@@ -250,7 +250,47 @@ def time_to_accuracy(solve, w, K, p_sweep=(0.1, 0.3, 0.5, 0.7)):
     key = f"pdhgskip_p{w.p}"
     if res.get(key, {}).get("ms") and res.get("pdhg_p1", {}).get("ms"):
         res["speedup_pdhgskip_vs_pdhg"] = round(res["pdhg_p1"]["ms"] / res[key]["ms"], 3)
+    if extra is not None:
+        res.update(extra(phis))
     return res
+
+
+def ct_comparisons(T, op, w, b, L, seed, K):
+    """The paper's comparison methods on the CT workload: PDHGSkip-1 at p in
+    {0.3, 0.7} (sigma = tau = 0.99 sqrt(p) / |A|, so that sigma tau (1 +
+    omega) |A|^2 < 1) and FISTA (step 1 / |A|^2), 50 inner iterations."""
+    import math
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    N, na, nd = w.H, w.n_ang, w.n_det
+    x = torch.zeros(N, N, device=dev)
+    q = torch.zeros(2, N, N, device=dev)
+    y = torch.zeros(na, nd, device=dev)
+
+    def entries(phis):
+        out = {}
+        for pp in (0.3, 0.7):
+            s = 0.99 * math.sqrt(pp) / L
+
+            def run(iters, obj=False, pp=pp, s=s):
+                for t in (x, q, y):
+                    t.zero_()
+                return T.tvs_pdhgskip1(op, b, x, q, y, w.alpha, s, s, pp, iters, w.inner_iters,
+                                       nonneg=1, seed=seed, graph=not obj, want_obj=obj,
+                                       want_theta=obj)
+            out[f"pdhgskip1_p{pp}"] = tta_entry(run, K, phis, f"pdhgskip1_p{pp}")
+
+        def run_f(iters, obj=False):
+            for t in (x, q):
+                t.zero_()
+            r = T.tvs_fista(op, b, x, q, w.alpha, 1.0 / L ** 2, iters, w.inner_iters, nonneg=1,
+                            graph=not obj, want_obj=obj)
+            r["theta"] = np.ones(iters, dtype=np.uint8)
+            return r
+        out["fista"] = tta_entry(run_f, K, phis, "fista")
+        return out
+    return entries
 
 
 def spdhg_tta(T, ctx, w, b, seed, K=6000, configs=((4, 0.1), (4, 0.3), (10, 0.1), (10, 0.3),
@@ -346,28 +386,38 @@ def small_tta(T, ctx):
 
         out = {"phi_star": phis, "dtype": w.dtype}
         for pp in tuple(w.p_sweep or (w.p,)) + (1.0,):
-            r = solve(pp, K, obj=True)
-            rel = np.abs(r["obj"] - phis) / phis
-            bad = np.nonzero(rel > 1e-4)[0]
-            kstar = int(bad[-1] + 2) if len(bad) else 1
             key = "pgd_p1" if pp == 1.0 else f"proxskip_p{pp}"
-            if kstar > K:
-                out[key] = {"iters": None, "note": f"not reached in {K} iterations",
-                            "final_rel": float(rel[-1])}
-                continue
-            times = []
-            for _ in range(3):
-                solve(pp, kstar)  # capture / warm
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                solve(pp, kstar)
-                e1.record()
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            out[key] = {"iters": kstar, "ms": round(float(np.median(times)), 3),
-                        "prox_calls": int(np.sum(r["theta"][:kstar])),
-                        "final_rel": float(rel[-1])}
+            out[key] = tta_entry(lambda iters, obj=False: solve(pp, iters, obj), K, phis,
+                                 f"{name} {key}")
+        if name == "deblur512":
+            # the paper's table of the deblurring comparison, on this workload:
+            # ProxSkip (p = 0.5, 10 inner; p = 0.05, 100 inner), ISTA (10
+            # inner) and FISTA (100 and 10 inner), to 1e-4, 3000 iterations
+            def psk(pp, kin):
+                def run(iters, obj=False):
+                    for t in (x, h, q):
+                        t.zero_()
+                    return T.tvs_proxskip(op, b, x, h, q, w.alpha, 1.0, pp, iters, kin, seed=seed,
+                                          graph=not obj, want_obj=obj, want_theta=obj)
+                return run
+
+            def fista(kin):
+                def run(iters, obj=False):
+                    for t in (x, q):
+                        t.zero_()
+                    r = T.tvs_fista(op, b, x, q, w.alpha, 1.0, iters, kin, graph=not obj,
+                                    want_obj=obj)
+                    r["theta"] = np.ones(iters, dtype=np.uint8)
+                    return r
+                return run
+
+            table = {}
+            for key, run in (("proxskip_p0.5_inner10", psk(0.5, 10)),
+                             ("proxskip_p0.05_inner100", psk(0.05, 100)),
+                             ("ista_inner10", psk(1.0, 10)),
+                             ("fista_inner100", fista(100)), ("fista_inner10", fista(10))):
+                table[key] = tta_entry(run, 3000, phis, f"deblur512 {key}")
+            out["paper_table"] = table
         T.tvs_op_destroy(op)
         res[name] = out
         log(f"time to 1e-4 ({name}): {out}")

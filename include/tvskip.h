@@ -291,6 +291,28 @@ tvs_status tvs_pdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
                         const tvs_params* params, double* obj_trace,
                         uint8_t* theta_trace, tvs_report* report);
 
+/* The paper's comparison methods on the same kernels.
+ * FISTA (Alg. "FISTA", its momentum read as Beck and Teboulle's):
+ *   ybar = x_k + ((t_k - 1) / t_{k+1}) (x_k - x_{k-1}),
+ *   x_{k+1} = prox_{gamma g}(ybar - gamma A^T (A ybar - b)) by FGP (warm dual),
+ * t_1 = 1 and x_{k-1} = x_k at the start of every call (momentum restarted).
+ * params: alpha, step = gamma, outer/inner iterations, nonneg, flags (p,
+ * seed, stream_id, k0, dual_step ignored; p must still be in (0, 1]).
+ * state: x, q (h, y unused).  ISTA is tvs_proxskip at p = 1. */
+tvs_status tvs_fista(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                     const tvs_params* params, double* obj_trace, tvs_report* report);
+
+/* PDHGSkip-1 (Alg. "PDHGSkip-1", the bracket read as K(x_{k+1} + xhat_k),
+ * omega + 1 = 1/p):
+ *   theta_k = 1: x+ = prox_{sigma g}(x_k - sigma A^T y_k) by FGP,
+ *                e = (1 + 1/p) x+ - x_k / p (= x_{k+1} + xhat_k), x_{k+1} = x+
+ *   theta_k = 0: x_{k+1} = e = x_k (no A^T, no prox)
+ *   y_{k+1} = (y_k + tau (A e - b)) / (1 + tau).
+ * At p = 1 this is PDHG.  Arguments as tvs_pdhgskip (state h unused). */
+tvs_status tvs_pdhgskip1(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                         const tvs_params* params, double* obj_trace, uint8_t* theta_trace,
+                         tvs_report* report);
+
 /* Stochastic angle subsets with the skipped prox (the paper's "Discussion
  * and Future work": a random subset of the projection angles per iteration
  * in addition to the random prox).  Reading: SPDHG (Chambolle, Ehrhardt,

@@ -25,7 +25,7 @@ __all__ = [
     "tvs_grad", "tvs_div", "tvs_tv_prox", "tvs_tv_prox_noalloc", "tvs_tv_gap", "tvs_objective",
     "tvs_coin",
     "tvs_proxskip", "tvs_pdhgskip", "tvs_proxskip_ex", "tvs_pdhgskip_ex",
-    "tvs_spdhgskip", "tvs_subset",
+    "tvs_spdhgskip", "tvs_subset", "tvs_fista", "tvs_pdhgskip1",
     "tvs_dual_rof_proxskip",
     "tvs_fgp_variant_count", "tvs_fgp_variant", "tvs_fgp_set_variant", "tvs_fgp_autotune",
     "tvs_proxskip_batched", "tvs_fgp_set_variant_batched", "tvs_fgp_autotune_batched",
@@ -273,6 +273,50 @@ def tvs_pdhgskip(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inne
     """PDHGSkip-2 in place on (x, h, q, y).  Returns dict(n_prox, iters, obj, theta)."""
     return _solve(lib().tvs_pdhgskip, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
                   inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta)
+
+
+def tvs_fista(op: int, b, x, q, alpha, step, outer_iters, inner_iters, nonneg=0, graph=False,
+              want_obj=False):
+    """FISTA with the FGP prox (momentum restarted per call), in place on
+    (x, q).  Returns dict(n_prox, iters, obj)."""
+    import numpy as np
+    d = _dtype_code(x)
+    n = x.numel()
+    st = tvs_state(_ptr(x), None, _ptr(q, 2 * n, d), None)
+    P = tvs_params(alpha=float(alpha), step=float(step), dual_step=0.0, p=1.0,
+                   outer_iters=int(outer_iters), inner_iters=int(inner_iters),
+                   nonneg=int(nonneg), seed=0, stream_id=0, k0=0,
+                   flags=TVS_FLAG_GRAPH if graph else 0, reserved=0)
+    rep = tvs_report()
+    obj = np.zeros(max(int(outer_iters), 1)) if want_obj else None
+    check(lib().tvs_fista(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st),
+                          C.byref(P), obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
+                          C.byref(rep)))
+    return dict(n_prox=rep.n_prox, iters=rep.iters, obj=obj[:outer_iters] if want_obj else None)
+
+
+def tvs_pdhgskip1(op: int, b, x, q, y, alpha, sigma, tau, p, outer_iters, inner_iters, nonneg=0,
+                  seed=0, stream_id=0, k0=0, graph=False, want_obj=False, want_theta=False):
+    """PDHGSkip-1 (omega + 1 = 1/p) in place on (x, q, y).  Returns dict(n_prox,
+    iters, obj, theta)."""
+    import numpy as np
+    d = _dtype_code(x)
+    n = x.numel()
+    st = tvs_state(_ptr(x), None, _ptr(q, 2 * n, d), _ptr(y, tvs_op_out_size(op), d))
+    P = tvs_params(alpha=float(alpha), step=float(sigma), dual_step=float(tau), p=float(p),
+                   outer_iters=int(outer_iters), inner_iters=int(inner_iters),
+                   nonneg=int(nonneg), seed=int(seed), stream_id=int(stream_id), k0=int(k0),
+                   flags=TVS_FLAG_GRAPH if graph else 0, reserved=0)
+    rep = tvs_report()
+    K = max(int(outer_iters), 1)
+    obj = np.zeros(K) if want_obj else None
+    th = np.zeros(K, dtype=np.uint8) if want_theta else None
+    check(lib().tvs_pdhgskip1(C.c_void_p(op), d, _ptr(b, tvs_op_out_size(op), d), C.byref(st),
+                              C.byref(P), obj.ctypes.data_as(C.POINTER(C.c_double)) if want_obj else None,
+                              th.ctypes.data_as(C.POINTER(C.c_uint8)) if want_theta else None,
+                              C.byref(rep)))
+    return dict(n_prox=rep.n_prox, iters=rep.iters, obj=obj[:outer_iters] if want_obj else None,
+                theta=th[:outer_iters] if want_theta else None)
 
 
 def tvs_spdhgskip(op: int, b, x, h, q, y, n_subsets, alpha, sigma, tau, p, outer_iters,

@@ -96,6 +96,10 @@ PROTOTYPES = {
     "tvs_objective": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp]),
     "tvs_coin": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_double]),
     "tvs_subset": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int]),
+    "tvs_fista": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params), dp,
+                            C.POINTER(tvs_report)]),
+    "tvs_pdhgskip1": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params), dp,
+                                C.POINTER(C.c_uint8), C.POINTER(tvs_report)]),
     "tvs_spdhgskip": (C.c_int, [vp, C.c_int, vp, C.POINTER(tvs_state), C.POINTER(tvs_params),
                                 C.c_int, dp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32),
                                 C.POINTER(tvs_report)]),

@@ -912,6 +912,155 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
     });
 }
 
+// ------------------------------------------------------- comparison methods
+// Alg. "FISTA" with the FGP prox (Beck-Teboulle momentum, restarted at every
+// call): ybar = x_k + beta_k (x_k - x_{k-1}), x_{k+1} = prox_{gamma g}(ybar -
+// gamma grad f(ybar)).  The data step at ybar is the ProxSkip data step with
+// a zero control variate and theta = 1 (v = ybar - gamma grad f(ybar)); the
+// iterates rotate through the caller's x and two scratch images.
+template <typename T>
+static void run_fista(tvs_op* op, const T* b, const tvs_state* st, const tvs_params* P,
+                      const std::vector<double>& beta, double* obj_dev) {
+    tvs_ctx* ctx = op->ctx;
+    const int H = op->H, W = op->W;
+    const size_t n = (size_t)H * W, m = op->out_size();
+    T* xs[3] = {(T*)st->x, (T*)scratch(ctx, S_FX1, n * sizeof(T)),
+                (T*)scratch(ctx, S_FX2, n * sizeof(T))};
+    T* q = (T*)st->q;
+    T* ybar = (T*)scratch(ctx, S_XBAR, n * sizeof(T));
+    T* hz = (T*)scratch(ctx, S_HZERO, n * sizeof(T));
+    T* xhat = (T*)scratch(ctx, S_XHAT, n * sizeof(T));
+    T* v = (T*)scratch(ctx, S_V, n * sizeof(T));
+    T* res = (T*)scratch(ctx, S_RES, m * sizeof(T));
+    T* xp = nullptr;
+    T* xTp = nullptr;
+    if (op->kind == OP_JOSEPH) {
+        xp = (T*)scratch(ctx, S_PADX, (size_t)H * (W + 2 * JPAD) * sizeof(T)) + JPAD;
+        xTp = (T*)scratch(ctx, S_TR_IMG, (size_t)W * (H + 2 * JPAD) * sizeof(T)) + JPAD;
+    }
+    launch_fill<T>(ctx, n, T(0), hz);
+    const double gamma = P->step;
+    const FgpConfig cfg = fgp_config(ctx, H, W, (int)sizeof(T));
+    PrimalStep<T> ps{};
+    ps.x = ybar;
+    ps.h = hz;
+    ps.xhat = xhat;
+    ps.v = v;
+    ps.step = (T)gamma;
+    ps.coef = T(0);
+    ps.theta = 1;
+    int cur = 0, prev = 0;  // x_{k-1} = x_k at the start of a call
+    for (int64_t k = 0; k < P->outer_iters; ++k) {
+        launch_fista_extrap<T>(ctx, n, xs[cur], xs[prev], (T)beta[k], ybar);
+        if (op->kind == OP_IDENTITY) {
+            launch_identity_step<T>(ctx, H, W, b, ps);
+        } else if (op->kind == OP_BLUR) {
+            launch_blur<T>(ctx, op, false, ybar, b, res);
+            launch_blur_adjoint_step<T>(ctx, op, res, ps);
+        } else {
+            launch_pad_copy<T>(ctx, H, W, ybar, xp, xTp);
+            launch_joseph_fwd<T>(ctx, op, xp, xTp, b, res, FWD_RESIDUAL, T(0));
+            launch_joseph_adj<T>(ctx, op, res, nullptr, &ps);
+        }
+        const int nxt = (cur != 0 && prev != 0) ? 0 : ((cur != 1 && prev != 1) ? 1 : 2);
+        T* qf = run_fgp<T>(ctx, H, W, v, P->alpha * gamma, P->inner_iters, P->nonneg, q, cfg);
+        Finalize<T> f{};
+        f.v = v;
+        f.q = qf;
+        f.q_out = q;
+        f.z = xs[nxt];
+        f.nonneg = P->nonneg;
+        f.mode = 0;
+        launch_finalize<T>(ctx, H, W, f);
+        prev = cur;
+        cur = nxt;
+        if (obj_dev) objective_dev<T>(op, b, xs[cur], P->alpha, obj_dev + k);
+    }
+    if (cur != 0) launch_copy<T>(ctx, n, xs[cur], xs[0]);
+}
+
+// Alg. "PDHGSkip-1" (omega + 1 = 1/p): theta_k = 1: x+ = prox_{sigma g}(x_k -
+// sigma K^T y_k) (the adjoint's primal-step epilogue with a zero control
+// variate gives x_k - sigma K^T y_k), e = (1 + 1/p) x+ - x_k / p (finalize
+// mode 4); theta_k = 0: x and e = x_k unchanged, neither K^T y nor the prox
+// is run.  Then y = (y + tau (K e - b)) / (1 + tau).
+template <typename T>
+static void run_pdhgskip1(tvs_op* op, const T* b, const tvs_state* st, const tvs_params* P,
+                          const std::vector<uint8_t>& theta, double* obj_dev) {
+    tvs_ctx* ctx = op->ctx;
+    const int H = op->H, W = op->W;
+    const size_t n = (size_t)H * W;
+    T* x = (T*)st->x;
+    T* q = (T*)st->q;
+    T* y = (T*)st->y;
+    T* hz = (T*)scratch(ctx, S_HZERO, n * sizeof(T));
+    T* xhat = (T*)scratch(ctx, S_XHAT, n * sizeof(T));
+    T* v = (T*)scratch(ctx, S_V, n * sizeof(T));
+    const bool jos = op->kind == OP_JOSEPH;
+    const int e_ld = jos ? W + 2 * JPAD : W, eT_ld = H + 2 * JPAD;
+    T* e = nullptr;
+    T* eT = nullptr;
+    if (jos) {
+        e = (T*)scratch(ctx, S_XBARP, (size_t)H * e_ld * sizeof(T)) + JPAD;
+        eT = (T*)scratch(ctx, S_XBARTP, (size_t)W * eT_ld * sizeof(T)) + JPAD;
+        launch_fill<T>(ctx, (size_t)H * e_ld, T(0), e - JPAD);
+        launch_fill<T>(ctx, (size_t)W * eT_ld, T(0), eT - JPAD);
+    } else {
+        e = (T*)scratch(ctx, S_XBAR, n * sizeof(T));
+    }
+    launch_fill<T>(ctx, n, T(0), hz);
+    const double sigma = P->step, p = P->p;
+    const T tau = (T)P->dual_step;
+    const FgpConfig cfg = fgp_config(ctx, H, W, (int)sizeof(T));
+    PrimalStep<T> ps{};
+    ps.x = x;
+    ps.h = hz;
+    ps.xhat = xhat;
+    ps.v = v;
+    ps.step = (T)sigma;
+    ps.coef = T(0);
+    ps.theta = 1;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        const T* ep;
+        if (theta[kk]) {
+            if (op->kind == OP_IDENTITY)
+                launch_identity_adj_step<T>(ctx, H, W, y, ps);
+            else if (op->kind == OP_BLUR)
+                launch_blur_adjoint_step<T>(ctx, op, y, ps);
+            else
+                launch_joseph_adj<T>(ctx, op, y, nullptr, &ps);
+            T* qf = run_fgp<T>(ctx, H, W, v, P->alpha * sigma, P->inner_iters, P->nonneg, q, cfg);
+            Finalize<T> f{};
+            f.v = v;
+            f.q = qf;
+            f.q_out = q;
+            f.x = x;
+            f.xbar = e;
+            f.xbarT = jos ? eT : nullptr;
+            f.xbar_ld = e_ld;
+            f.xbarT_ld = eT_ld;
+            f.c1 = (T)(1.0 + 1.0 / p);
+            f.c2 = (T)(1.0 / p);
+            f.nonneg = P->nonneg;
+            f.mode = 4;
+            launch_finalize<T>(ctx, H, W, f);
+            ep = e;
+        } else if (jos) {
+            launch_pad_copy<T>(ctx, H, W, x, e, eT);
+            ep = e;
+        } else {
+            ep = x;
+        }
+        if (op->kind == OP_IDENTITY)
+            launch_dual_prox_pointwise<T>(ctx, n, ep, b, y, tau);
+        else if (op->kind == OP_BLUR)
+            launch_blur_dual_prox<T>(ctx, op, ep, b, y, tau);
+        else
+            launch_joseph_fwd<T>(ctx, op, ep, eT, b, y, FWD_DUAL_PROX, tau);
+        if (obj_dev) objective_dev<T>(op, b, x, P->alpha, obj_dev + kk);
+    }
+}
+
 // ------------------------------------------- stochastic angle subsets
 // SPDHG over the n angle subsets with the prox skipped as in PDHGSkip-2
 // (the paper's "Discussion and Future work"):
@@ -1090,7 +1239,112 @@ static tvs_status spdhg_solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_st
     });
 }
 
+template <typename T>
+static void prepare_cmp(tvs_op* op, bool skip1, const tvs_params* P) {
+    tvs_ctx* ctx = op->ctx;
+    const size_t n = (size_t)op->H * op->W, m = op->out_size();
+    for (Slot s : {S_XHAT, S_V, S_HZERO}) scratch(ctx, s, n * sizeof(T));
+    if (!skip1)
+        for (Slot s : {S_FX1, S_FX2, S_XBAR}) scratch(ctx, s, n * sizeof(T));
+    scratch(ctx, S_RES, m * sizeof(T));
+    if (op->kind == OP_JOSEPH) {
+        const size_t rows = (size_t)op->H * (op->W + 2 * JPAD), cols = (size_t)op->W * (op->H + 2 * JPAD);
+        scratch(ctx, skip1 ? S_XBARP : S_PADX, rows * sizeof(T));
+        scratch(ctx, skip1 ? S_XBARTP : S_TR_IMG, cols * sizeof(T));
+        if (sizeof(T) == 4 && op->joseph.rd_ok)
+            scratch(ctx, S_PARTIMG, (size_t)joseph_rd_groups(ctx, op) * n * sizeof(T));
+    } else if (skip1) {
+        scratch(ctx, S_XBAR, n * sizeof(T));
+    }
+    scratch(ctx, S_Q1, 2 * n * sizeof(T));
+    scratch(ctx, S_Q2, 2 * n * sizeof(T));
+    scratch(ctx, S_Q3, 2 * n * sizeof(T));
+    beta_table_dev<T>(ctx, P->inner_iters + 1);
+}
+
+// FISTA (skip1 = false) and PDHGSkip-1 (skip1 = true): host-side schedule
+// (momentum coefficients / coin), optional graph capture, traces.
+static tvs_status cmp_solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* st,
+                            const tvs_params* P, double* obj_trace, uint8_t* theta_trace,
+                            tvs_report* report, bool skip1) {
+    return guarded([&] {
+        TVS_REQUIRE(op && b && st, TVS_ERR_INVALID_ARG, "null pointer");
+        check_dtype(dtype);
+        check_params(P, skip1);
+        TVS_REQUIRE(st->x && st->q, TVS_ERR_INVALID_ARG, "state x, q required");
+        TVS_REQUIRE(!skip1 || st->y, TVS_ERR_INVALID_ARG, "state y required for PDHGSkip-1");
+        tvs_ctx* ctx = op->ctx;
+        use_device(ctx);
+        const int64_t K = P->outer_iters;
+        std::vector<uint8_t> theta((size_t)K, 1);
+        std::vector<double> beta((size_t)K, 0.0);
+        int64_t nprox = K;
+        if (skip1) {
+            nprox = 0;
+            for (int64_t kk = 0; kk < K; ++kk) {
+                theta[kk] = (uint8_t)coin(P->seed, P->stream_id, P->k0 + kk, P->p);
+                nprox += theta[kk];
+            }
+        } else {
+            double t = 1.0;
+            for (int64_t kk = 0; kk < K; ++kk) {
+                const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+                beta[kk] = (t - 1.0) / tn;
+                t = tn;
+            }
+        }
+        double* obj_dev = nullptr;
+        if (obj_trace && K > 0) obj_dev = (double*)scratch(ctx, S_OBJ, (size_t)K * sizeof(double));
+        const bool use_graph = (P->flags & TVS_FLAG_GRAPH) && !obj_dev && K > 0;
+        if (dtype == TVS_F32)
+            prepare_cmp<float>(op, skip1, P);
+        else
+            prepare_cmp<double>(op, skip1, P);
+        auto enqueue = [&] {
+            if (dtype == TVS_F32) {
+                if (skip1)
+                    run_pdhgskip1<float>(op, (const float*)b, st, P, theta, obj_dev);
+                else
+                    run_fista<float>(op, (const float*)b, st, P, beta, obj_dev);
+            } else {
+                if (skip1)
+                    run_pdhgskip1<double>(op, (const double*)b, st, P, theta, obj_dev);
+                else
+                    run_fista<double>(op, (const double*)b, st, P, beta, obj_dev);
+            }
+        };
+        if (use_graph) {
+            std::vector<uint64_t> key = graph_key(op, skip1, (int)dtype, b, st, P);
+            key.insert(key.end(), {skip1 ? 0x5C1ULL : 0xF157AULL});
+            graph_run_key(ctx, key, enqueue);
+        } else {
+            enqueue();
+        }
+        if (theta_trace && K > 0) std::memcpy(theta_trace, theta.data(), (size_t)K);
+        if (obj_dev) {
+            TVS_HIP(hipMemcpyAsync(obj_trace, obj_dev, (size_t)K * sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            TVS_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        if (report) {
+            report->n_prox = nprox;
+            report->iters = K;
+        }
+    });
+}
+
 }  // namespace tvs
+
+extern "C" tvs_status tvs_fista(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                                const tvs_params* params, double* obj_trace, tvs_report* report) {
+    return cmp_solve(op, dtype, b, state, params, obj_trace, nullptr, report, false);
+}
+
+extern "C" tvs_status tvs_pdhgskip1(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
+                                    const tvs_params* params, double* obj_trace,
+                                    uint8_t* theta_trace, tvs_report* report) {
+    return cmp_solve(op, dtype, b, state, params, obj_trace, theta_trace, report, true);
+}
 
 extern "C" tvs_status tvs_spdhgskip(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,
                                     const tvs_params* params, int n_subsets, double* obj_trace,

@@ -810,9 +810,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
         qu[p] = ok && i > 0 ? qy[g - W] : T(0);
         ql[p] = ok && j > 0 ? qx[g - 1] : T(0);
         vv[p] = ok ? f.v[g] : T(0);
-        xh[p] = ok && f.mode != 0 ? f.xhat[g] : T(0);
-        hh[p] = ok && f.mode != 0 ? f.h[g] : T(0);
-        xo[p] = ok && f.mode == 2 ? f.x[g] : T(0);
+        xh[p] = ok && f.mode != 0 && f.mode != 4 ? f.xhat[g] : T(0);
+        hh[p] = ok && f.mode != 0 && f.mode != 4 ? f.h[g] : T(0);
+        xo[p] = ok && (f.mode == 2 || f.mode == 4) ? f.x[g] : T(0);
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -835,11 +835,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
         if (f.mode == 0) {
             f.z[g] = z;
         } else {
-            f.h[g] = hh[p] + f.rate * (z - xh[p]);
+            if (f.mode != 4) f.h[g] = hh[p] + f.rate * (z - xh[p]);
             if (f.mode >= 2) {
                 // PDHGSkip-2 extrapolates; the stochastic-angle method
-                // (mode 3) takes x+ itself
-                const T xb = f.mode == 3 ? z : T(2) * z - xo[p];
+                // (mode 3) takes x+ itself; PDHGSkip-1 (mode 4) forms
+                // x_{k+1} + xhat_k = c1 x+ - c2 x_k
+                const T xb = f.mode == 3 ? z : (f.mode == 4 ? f.c1 * z - f.c2 * xo[p] : T(2) * z - xo[p]);
                 f.xbar[(size_t)i * f.xbar_ld + j] = xb;
                 s_t[li][lj] = xb;
             }

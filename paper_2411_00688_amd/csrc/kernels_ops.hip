@@ -119,6 +119,20 @@ __global__ __launch_bounds__(256) void transpose_kernel(int H, int W, const T* x
     }
 }
 
+template <typename T>
+__global__ void fista_extrap_kernel(size_t n, const T* x, const T* xprev, T beta, T* out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = x[i] + beta * (x[i] - xprev[i]);
+}
+
+template <typename T>
+void launch_fista_extrap(tvs_ctx* ctx, size_t n, const T* x, const T* xprev, T beta, T* out) {
+    hipLaunchKernelGGL((fista_extrap_kernel<T>), dim3(grid1d(n)), dim3(256), 0, ctx->stream, n, x,
+                       xprev, beta, out);
+    TVS_LAUNCH_CHECK();
+}
+
 // Row permutation of a rows x cols array: gather dst[r] = src[perm[r]], or
 // scatter dst[perm[r]] = src[r].
 template <typename T>
@@ -1162,6 +1176,7 @@ void launch_joseph_adj(tvs_ctx* ctx, const tvs_op* op, const T* y, T* x_out,
     template void launch_fill<T>(tvs_ctx*, size_t, T, T*);                                       \
     template void launch_transpose<T>(tvs_ctx*, int, int, const T*, T*);                         \
     template void launch_permute_rows<T>(tvs_ctx*, int, int, const int*, const T*, T*, bool);    \
+    template void launch_fista_extrap<T>(tvs_ctx*, size_t, const T*, const T*, T, T*);          \
     template void launch_identity_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&);   \
     template void launch_identity_adj_step<T>(tvs_ctx*, int, int, const T*, const PrimalStep<T>&); \
     template void launch_dual_prox_pointwise<T>(tvs_ctx*, size_t, const T*, const T*, T*, T);    \

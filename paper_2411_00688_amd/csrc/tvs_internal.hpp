@@ -52,7 +52,7 @@ enum Slot : int {
     S_XHAT = 0, S_V, S_XBAR, S_XBART, S_Q1, S_Q2, S_Q3, S_RES, S_TMP, S_BETAF,
     S_PART, S_RED, S_BETA, S_Z, S_NORMV, S_OBJ, S_TR_IMG, S_PARTIMG, S_XBARP, S_XBARTP,
     S_PADX, S_BSL, S_BLIST, S_BTHETA, S_BPREF, S_GATE, S_QNET, S_SEL,
-    S_SB, S_SY, S_SDY, S_SZ, S_SZB, S_COUNT
+    S_SB, S_SY, S_SDY, S_SZ, S_SZB, S_FX1, S_FX2, S_HZERO, S_COUNT
 };
 
 struct GraphEntry;
@@ -253,8 +253,10 @@ struct Finalize {
     T* xbarT;        // pdhg: transposed copy (row stride xbarT_ld)
     int xbar_ld, xbarT_ld;
     T rate;
+    T c1, c2;        // mode 4: xbar = c1 z - c2 x_old
     int nonneg;
-    int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip, 3: stochastic angles (xbar = z)
+    int mode;        // 0: prox only, 1: proxskip, 2: pdhgskip, 3: stochastic angles (xbar = z),
+                     // 4: pdhgskip-1 (no control variate)
 };
 template <typename T> void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f);
 
@@ -272,6 +274,9 @@ template <typename T>
 void launch_axpby(tvs_ctx* ctx, size_t n, T a, const T* x, T bcoef, const T* y, T* out);
 template <typename T> void launch_copy(tvs_ctx* ctx, size_t n, const T* x, T* y);
 template <typename T> void launch_fill(tvs_ctx* ctx, size_t n, T val, T* y);
+// FISTA's extrapolation: out = x + beta (x - xprev).
+template <typename T>
+void launch_fista_extrap(tvs_ctx* ctx, size_t n, const T* x, const T* xprev, T beta, T* out);
 template <typename T>
 void launch_permute_rows(tvs_ctx* ctx, int rows, int cols, const int* perm, const T* src, T* dst,
                          bool scatter);
