@@ -327,6 +327,9 @@ void joseph_upload(tvs_op* op) {
     JosephGeom& g = op->joseph;
     g.rd_ok = true;
     for (const JAngle& e : g.host) g.rd_ok = g.rd_ok && joseph_rd_angle_ok(e);
+    g.pair_ok = true;
+    for (const JAngle& e : g.host)
+        g.pair_ok = g.pair_ok && std::fabs(e.Aq) >= 4294967296.0 && std::fabs(e.Aq) < 8589934592.0;
     TVS_HIP(hipMalloc(&g.ang, g.n_ang * sizeof(JAngle)));
     TVS_HIP(hipMemcpy(g.ang, g.host.data(), g.n_ang * sizeof(JAngle), hipMemcpyHostToDevice));
 }

@@ -566,6 +566,138 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
     }
 }
 
+// Paired-ray projector (float32, padded copies within 4 GiB, 1 <= |A| < 2).
+// Lane l of a block takes the adjacent bins d = 2 l and d + 1 of one angle:
+// their samples are 1 to 2 pixels apart along the interpolation axis, so one
+// 16-byte gather of four consecutive pixels from the floor of the smaller
+// sample position holds both rays' neighbour pairs.
+// Half as many vector-memory instructions as one ray per lane (the texture
+// unit handles a quarter-wave per clock whatever the width), the same
+// arithmetic per ray in the same order, so the sums equal
+// joseph_fwd_kernel's bit for bit.  The gather start is clamped into the
+// padded row [-JPAD, n_int], so every load stays inside the copy.
+// The steps of one pair of rays: ray a at Ua, ray b at Ua + dA (dA = the
+// bin step), both advancing by dB per step; NEG: ray b lies left of ray a.
+template <bool NEG>
+__device__ __forceinline__ void pair_walk(const char* img0, long long Ua, long long dA,
+                                          long long dB, int ro, int ld, int n_int, int n,
+                                          float& acc0a, float& acc1a, float& acc0b,
+                                          float& acc1b) {
+    long long Ub = Ua + dA;
+    int s = 0;
+    // four gathers in flight before their sums
+    for (; s + 4 <= n; s += 4) {
+        float4 p[4];
+        unsigned fa[4], fb[4];
+        int j[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ha = (int)(Ua >> 32), hb = (int)(Ub >> 32);
+            int c = NEG ? hb : ha;
+            c = c < -JPAD ? -JPAD : (c > n_int ? n_int : c);  // stay inside the padded row
+            __builtin_memcpy(&p[k], img0 + ((unsigned)(ro + c) << 2), sizeof(float4));
+            fa[k] = (unsigned)Ua;
+            fb[k] = (unsigned)Ub;
+            j[k] = NEG ? ha - hb : hb - ha;  // the right ray's pair: 1 or 2 pixels further
+            Ua += dB;
+            Ub += dB;
+            ro += ld;
+            // one induction variable each (the compiler would otherwise keep
+            // a copy of each position per unrolled step)
+            __asm__("" : "+v"(Ua), "+v"(Ub));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float q0 = j[k] == 1 ? p[k].y : p[k].z, q1 = j[k] == 1 ? p[k].z : p[k].w;
+            const float va0 = NEG ? q0 : p[k].x, va1 = NEG ? q1 : p[k].y;
+            const float vb0 = NEG ? p[k].x : q0, vb1 = NEG ? p[k].y : q1;
+            acc0a += va0;
+            acc1a = fmaf((float)fa[k], va1 - va0, acc1a);
+            acc0b += vb0;
+            acc1b = fmaf((float)fb[k], vb1 - vb0, acc1b);
+        }
+    }
+    for (; s < n; ++s) {
+        const int ha = (int)(Ua >> 32), hb = (int)(Ub >> 32);
+        int c = NEG ? hb : ha;
+        c = c < -JPAD ? -JPAD : (c > n_int ? n_int : c);
+        float4 p;
+        __builtin_memcpy(&p, img0 + ((unsigned)(ro + c) << 2), sizeof(float4));
+        const int j = NEG ? ha - hb : hb - ha;
+        const float q0 = j == 1 ? p.y : p.z, q1 = j == 1 ? p.z : p.w;
+        const float va0 = NEG ? q0 : p.x, va1 = NEG ? q1 : p.y;
+        const float vb0 = NEG ? p.x : q0, vb1 = NEG ? p.y : q1;
+        acc0a += va0;
+        acc1a = fmaf((float)(unsigned)Ua, va1 - va0, acc1a);
+        acc0b += vb0;
+        acc1b = fmaf((float)(unsigned)Ub, vb1 - vb0, acc1b);
+        Ua += dB;
+        Ub += dB;
+        ro += ld;
+    }
+}
+
+template <int SEG>
+__global__ __launch_bounds__(64 * SEG) void joseph_fwd_pair_kernel(JFwdArgs<float> a) {
+    __shared__ float part[SEG][128];
+    const JAngle g = a.ang[blockIdx.y];
+    const int lane = (int)threadIdx.x & 63;
+    const int seg = (int)threadIdx.x >> 6;
+    const int d0 = (int)blockIdx.x * 128 + 2 * lane;
+    const int n_step = g.cls ? a.W : a.H;
+    const int n_int = g.cls ? a.H : a.W;
+    const float* img = g.cls ? a.xT : a.x;
+    const int ld = g.cls ? a.xT_ld : a.x_ld;
+    const int s0 = (seg * n_step) / SEG, s1 = ((seg + 1) * n_step) / SEG;
+    const bool neg = g.A < 0.0;  // wave-uniform: which ray of the pair lies left
+    float acc0a = 0.0f, acc1a = 0.0f, acc0b = 0.0f, acc1b = 0.0f;
+    if (d0 < a.n_det) {
+        // steps where either ray's sample can touch the image: with
+        // u_a = A d0 + B s + C and u_b = u_a + A, the union of -1 <= u < n_int
+        // over both is -1 - max(A, 0) <= u_a < n_int - min(A, 0)
+        const double base = fma(g.A, (double)d0, g.C);
+        const double ulo = -1.0 - (g.A > 0.0 ? g.A : 0.0), uhi = (double)n_int - (g.A < 0.0 ? g.A : 0.0);
+        int lo = s0, hi = s1;
+        if (g.B != 0.0) {
+            double t1 = (ulo - base) / g.B, t2 = (uhi - base) / g.B;
+            double tmin = t1 < t2 ? t1 : t2, tmax = t1 < t2 ? t2 : t1;
+            const double cl = (double)(s0 - 1), ch = (double)(s1 + 1);
+            tmin = tmin > cl ? (tmin < ch ? tmin : ch) : cl;
+            tmax = tmax < ch ? (tmax > cl ? tmax : cl) : ch;
+            const int a_lo = (int)floor(tmin), a_hi = (int)ceil(tmax) + 1;
+            lo = a_lo > lo ? a_lo : lo;
+            hi = a_hi < hi ? a_hi : hi;
+        } else if (!(base >= ulo && base < uhi)) {
+            hi = lo;
+        }
+        const int s_lo = lo > 0 ? lo : 0;
+        // 32.32 positions of both rays relative to their row; the row's
+        // element offset in the padded copy (pads included) advances
+        // separately, and a gather's byte offset (within 4 GiB) is formed
+        // from it and the clamped start in one instruction
+        const long long Ua0 = g.Aqi * (long long)d0 + g.Cqi + g.Bqi * (long long)s_lo;
+        const char* img0 = (const char*)(img - JPAD);
+        const int ro0 = s_lo * ld + JPAD;
+        if (neg)
+            pair_walk<true>(img0, Ua0, g.Aqi, g.Bqi, ro0, ld, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
+        else
+            pair_walk<false>(img0, Ua0, g.Aqi, g.Bqi, ro0, ld, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
+    }
+    part[seg][2 * lane] = acc0a + acc1a * 2.3283064365386963e-10f;
+    part[seg][2 * lane + 1] = acc0b + acc1b * 2.3283064365386963e-10f;
+    __syncthreads();
+    // the block's 128 bins, one per thread of the first two wavefronts
+    const int t = (int)threadIdx.x;
+    const int d = (int)blockIdx.x * 128 + t;
+    if (t < 128 && d < a.n_det) {
+        float sum = part[0][t];
+#pragma unroll
+        for (int k = 1; k < SEG; ++k) sum += part[k][t];
+        sum *= (float)g.wgt;
+        fwd_epilogue<float>(a.epi, (size_t)blockIdx.y * a.n_det + d, sum, a.b, a.y, a.dy, a.tau);
+    }
+}
+
 template <typename T>
 void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, const T* b, T* y,
                        int epi, T tau, T* dy) {
@@ -585,6 +717,14 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
     a.tau = tau;
     a.small = (size_t)op->H * a.x_ld * sizeof(T) < (1ull << 32) &&
               (size_t)op->W * a.xT_ld * sizeof(T) < (1ull << 32);
+    if constexpr (sizeof(T) == 4) {
+        if (a.small && op->joseph.pair_ok) {
+            hipLaunchKernelGGL((joseph_fwd_pair_kernel<8>), dim3(div_up(a.n_det, 128), op->joseph.n_ang),
+                               dim3(512), 0, ctx->stream, a);
+            TVS_LAUNCH_CHECK();
+            return;
+        }
+    }
     dim3 grid(div_up(a.n_det, 64), op->joseph.n_ang);
     hipLaunchKernelGGL((joseph_fwd_kernel<T, 8>), grid, dim3(512), 0, ctx->stream, a);
     TVS_LAUNCH_CHECK();

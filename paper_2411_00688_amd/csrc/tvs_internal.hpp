@@ -135,6 +135,11 @@ struct JosephGeom {
     // the ray-driven float32 backprojector applies (joseph_rd_angle_ok for
     // every angle)
     bool rd_ok = false;
+    // the paired-ray float32 projector applies: adjacent rays 1 to 2 pixels
+    // apart along the interpolation axis for every angle (1 <= |A| < 2 in
+    // the 32.32 coefficient), so a ray's right neighbour pair is 1 or 2
+    // pixels past the left ray's
+    bool pair_ok = false;
     // angle groups of the ray-driven backprojector, chosen on first use
     mutable int rd_groups = 0;
     // angle-subset operators of the stochastic-angle method (sub_n of them,
