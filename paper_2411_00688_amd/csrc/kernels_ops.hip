@@ -1075,8 +1075,10 @@ __device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long lo
     }
 }
 
-// All angles of one class of the block's group for wavefront w.
-template <int CLS>
+// All angles of one class of the block's group for wavefront w (FULL: the
+// strip has all RD_L steps, decided once for the loop so that the
+// accumulators stay in place from one angle to the next).
+template <int CLS, bool FULL>
 __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float (*yS)[RD_NB],
                                          const int* wst, const int* ecls, const int (*eD)[4],
                                          const long long (*eK)[4], int g, int G, int na_g,
@@ -1092,22 +1094,28 @@ __device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float
         bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
         const float val = yS[m][bi];
         const long long U = K + gg.Aqi * (long long)lane;
-        if (n_s >= RD_L)
-            rd_angle<true>(lane, n_s, U, gg.Bqi, val, acc);
-        else
-            rd_angle<false>(lane, n_s, U, gg.Bqi, val, acc);
+        rd_angle<FULL>(lane, n_s, U, gg.Bqi, val, acc);
     }
 }
 
 __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a) {
-    __shared__ float yS[RD_MAXA][RD_NB];
+    // the staged sinogram windows and, once every angle is done, the two
+    // transposition tiles share one buffer
+    __shared__ union {
+        float yS[RD_MAXA][RD_NB];
+        struct {
+            float tileT[RD_P][RD_P + 1];
+            float rowS[RD_P][RD_P + 1];
+        } t;
+    } sm;
+    float (*yS)[RD_NB] = sm.yS;
+    float (*tileT)[RD_P + 1] = sm.t.tileT;
+    float (*rowS)[RD_P + 1] = sm.t.rowS;
     __shared__ int wst[RD_MAXA];
     __shared__ int ecls[RD_MAXA];
     __shared__ float wgtS[RD_MAXA];
     __shared__ int eD[RD_MAXA][4];
     __shared__ long long eK[RD_MAXA][4];
-    __shared__ float tileT[RD_P][RD_P + 1];
-    __shared__ float rowS[RD_P][RD_P + 1];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
     const int tiles_x = div_up(a.W, RD_P), tiles = tiles_x * div_up(a.H, RD_P);
@@ -1155,8 +1163,15 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
     const int nR = __builtin_amdgcn_readfirstlane(a.H - (i0 + RD_L * w));
     const int nC = __builtin_amdgcn_readfirstlane(a.W - (j0 + RD_L * w));
-    rd_class<0>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
-    rd_class<1>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+    if (nR >= RD_L)
+        rd_class<0, true>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
+    else
+        rd_class<0, false>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
+    if (nC >= RD_L)
+        rd_class<1, true>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+    else
+        rd_class<1, false>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+    __syncthreads();  // every wavefront is done with yS, which tileT and rowS overlay
     // Column-stepping sums are held per (column = 13 w + k, row = lane) and
     // are transposed through tileT.  The last set stores both its sums, the
     // sets before it add theirs in place in descending order, and set 0 adds
