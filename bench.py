@@ -47,6 +47,17 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-prox training and runs")
     ap.add_argument("--no-light", action="store_true", help="skip the Dual-ROF / Huber runs")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched-form run (one warm and one timed batched solve, no "
+                         "per-slice comparison): the program to profile for the batched FGP "
+                         "kernels; prints a batched record, not the benchmark line")
+    ap.add_argument("--batched-outer", type=int, default=500,
+                    help="with --batched-only: outer iterations of the batched solve")
+    ap.add_argument("--tune-save", default=None,
+                    help="with --batched-only: write the run's FGP tuning table to this file")
+    ap.add_argument("--tune-load", default=None,
+                    help="with --batched-only: take the FGP tuning table from this file (no "
+                         "tuning sweeps in the run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel launches (event times, FGP HBM rate, the copy that "
                          "calibrates byte counters): the short program to run under rocprofv3 "
@@ -71,6 +82,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.init()
+    if args.batched_only:
+        res = batched_bench(T, K=args.batched_outer, plain=False, tune_load=args.tune_load,
+                            tune_save=args.tune_save)
+        print(json.dumps({"record": "batched", **res}), flush=True)
+        return
     w = synth.WORKLOADS["ct512"]
     N, na, nd = w.H, w.n_ang, w.n_det
     ang = synth.parallel_beam_angles(na)
@@ -147,8 +163,13 @@ def main():
     dom = "joseph_adj" if ps_ms["joseph_adj"] >= ps_ms["fgp_prox"] else "fgp_prox"
     roof = roofline(dom, kern, N, na, nd, Kin)
 
-    # ---- FGP on a large image: true HBM rate of the TV-prox kernel
+    # ---- FGP on a large image: true HBM rate of the TV-prox kernel; and at the
+    # workload's own 512^2 (working set resident in the last-level cache), in
+    # a context of its own so that the run's tuning table stays as it is
     fgp_big = fgp_hbm(T, ctx, args.fgp_size, Kin)
+    ctx512 = T.tvs_ctx_create(0)
+    fgp_512 = fgp_hbm(T, ctx512, N, Kin, resident=True)
+    T.tvs_ctx_destroy(ctx512)
 
     # ---- batched form: 256 uneven denoising slices in one graph vs one solve per slice
     batched = None
@@ -196,6 +217,7 @@ def main():
         "kernels_ms_per_step": trace_per_step(K),
         "roofline": roof,
         "tv_prox_hbm": fgp_big,
+        "tv_prox_512": fgp_512,
         "batched": batched,
         "learned": learned_res,
         "light_prox": light,
@@ -549,13 +571,16 @@ def roofline(dom, kern, N, na, nd, Kin):
             "launch_ms": round(ms, 5)}
 
 
-def fgp_hbm(T, ctx, n, Kin):
+def fgp_hbm(T, ctx, n, Kin, resident=False):
     """FGP at n x n float32 (working set far beyond the 256 MB last-level
     cache): a one-iteration-per-launch variant moves exactly the algorithmic
     28 B/px (read q_{k-1}, q_{k-2}, v; write q_k), so its GB/s is an HBM rate
     (the fastest such variant, tiles or row-walking strips, is reported next
     to torch's 1 GiB device copy on the same GPU); the tuned temporally
-    blocked variant is reported as an effective rate."""
+    blocked variant is reported as an effective rate.  resident: an image
+    whose working set stays in the last-level cache (512^2: 7.3 MB), where
+    every rate is an effective one (algorithmic bytes over time), not HBM
+    traffic."""
     import torch
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev).manual_seed(1)
@@ -579,6 +604,16 @@ def fgp_hbm(T, ctx, n, Kin):
     res["one_iter_per_launch"] = max(ts1, key=lambda r: r["GB/s"])
     vi, _ = T.tvs_fgp_autotune(ctx, T.TVS_F32, n, n, iters, 1)
     res["tuned"] = rate(vi)
+    if resident:
+        for key in ("one_iter_per_launch", "tuned"):
+            r = res[key]
+            r["effective_GB/s"] = r.pop("GB/s")
+            r["effective_frac_of_hbm_peak"] = r.pop("frac_of_hbm_peak")
+        res["note"] = ("working set resident in the last-level cache: effective rates "
+                       "(28 B/px per iteration over time), not HBM traffic")
+        T.tvs_fgp_set_variant(ctx, T.TVS_F32, n, n, -1)
+        log(f"FGP {n}^2 (cache-resident): {res}")
+        return res
     # a plain device copy of 1 GiB: the rate this GPU reaches on pure streaming
     a = torch.empty(1 << 28, device=dev)
     b = torch.empty_like(a)
@@ -854,7 +889,27 @@ def learned_bench(T, ctx, op, w, b, sigma, tau, seed, tta, steps=3000):
     return res
 
 
-def batched_bench(T, K=500, Kin=50):
+BATCHED_SUMMARY = os.path.join(ROOT, "profiles", "fgp_batched_c4.md")
+
+
+def batched_fgp_record():
+    """The committed rocprofv3 record of the batched FGP kernels in one
+    batched solve (kernel time and counter bytes), or None when a source it
+    depends on changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(BATCHED_SUMMARY).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        for src, want in rec["source_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != want:
+                return None
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    return rec
+
+
+def batched_bench(T, K=500, Kin=50, plain=True, tune_load=None, tune_save=None):
     """The batched workload (256 slices, sizes 128..1024 squared, per-slice
     alpha and p, A = I, gamma = 1, 500 outer iterations, 50 FGP iterations):
     one batched run captured in a HIP graph, against the plain method, one
@@ -884,16 +939,25 @@ def batched_bench(T, K=500, Kin=50):
     q = torch.zeros(2 * total, device=dev)
     ctx = T.tvs_ctx_create(0)  # its own tuning table
     tuned = {}
-    for n in sorted({s["H"] for s in sp}):
-        vi, _ = T.tvs_fgp_autotune(ctx, T.TVS_F32, n, n, Kin, 2)
-        tuned[str(n)] = list(T.tvs_fgp_variant(vi))
-    vb, _ = T.tvs_fgp_autotune_batched(ctx, T.TVS_F32, slices, Kin, 2)
+    if tune_load:
+        T.tvs_tune_load(ctx, tune_load)
+        for n in sorted({s["H"] for s in sp}):
+            tuned[str(n)] = list(T.tvs_fgp_variant(T.tvs_fgp_query(ctx, T.TVS_F32, n, n)[0]))
+        vb = T.tvs_fgp_query_batched(ctx, T.TVS_F32, len(slices))[0]
+    else:
+        for n in sorted({s["H"] for s in sp}):
+            vi, _ = T.tvs_fgp_autotune(ctx, T.TVS_F32, n, n, Kin, 2)
+            tuned[str(n)] = list(T.tvs_fgp_variant(vi))
+        vb, _ = T.tvs_fgp_autotune_batched(ctx, T.TVS_F32, slices, Kin, 2)
+    if tune_save:
+        T.tvs_tune_save(ctx, tune_save)
 
     def run_batched():
         for t in (x, h, q):
             t.zero_()
         return T.tvs_proxskip_batched(ctx, slices, b, x, h, q, 1.0, K, Kin, graph=True)
 
+    log(f"batched: {len(slices)} slices, {K} outer iterations: warm run")
     nprox = run_batched()                       # capture + warm
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -902,6 +966,20 @@ def batched_bench(T, K=500, Kin=50):
     e1.record()
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1)
+    # algorithmic FGP bytes of the solve: 28 B/px per FGP iteration (read two
+    # dual iterates and v, write one) over every slice's prox calls
+    nprox = np.asarray(nprox)
+    alg = 28.0 * Kin * float(sum(int(c) * s["H"] * s["W"] for c, s in zip(nprox, sp)))
+    if not plain:
+        res = {"slices": len(slices), "outer_iters": K, "inner_iters": Kin,
+               "prox_calls": int(np.sum(nprox)), "batched_ms": round(ms_b, 2),
+               "fgp_algorithmic_bytes_per_solve": alg,
+               "fgp_variant_batched": list(T.tvs_fgp_variant(vb))}
+        log(f"batched: {res}")
+        del x, h, q, b
+        T.tvs_ctx_destroy(ctx)
+        torch.cuda.empty_cache()
+        return res
     # plain method: one solve per slice (stream launches, the faster of the two
     # single-image modes for short runs; a graph per slice pays its capture)
     ops = {}
@@ -940,7 +1018,28 @@ def batched_bench(T, K=500, Kin=50):
            "batched_ms": round(ms_b, 2), "plain_per_slice_ms": round(ms_p, 2),
            "speedup": round(ms_p / ms_b, 3),
            "batched_Gpx_iters_per_s": round(px * K / (ms_b * 1e-3) / 1e9, 3),
-           "fgp_variant_batched": list(T.tvs_fgp_variant(vb)), "fgp_variant_per_size": tuned}
+           "fgp_variant_batched": list(T.tvs_fgp_variant(vb)), "fgp_variant_per_size": tuned,
+           "fgp_algorithmic_bytes_per_solve": alg}
+    # roofline of the batched FGP kernels: their time in one solve and their
+    # counter bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    # committed rocprofv3 record of the same solve
+    # (profiled on a shorter batched solve of the same slices and variants:
+    # counter collection serialises every launch)
+    rec = batched_fgp_record()
+    if rec and rec.get("slices") == len(slices) and rec.get("inner_iters") == Kin:
+        t = rec["fgp_kernel_ms_per_solve"] * 1e-3
+        a = rec["algorithmic_bytes_per_solve"]
+        meas = rec["fetch_bytes_per_solve"] + rec["write_bytes_per_solve"]
+        res["fgp_roofline"] = {
+            "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+            "profiled_solve_outer_iters": rec["outer_iters"],
+            "kernel_ms_per_solve": rec["fgp_kernel_ms_per_solve"],
+            "algorithmic_bytes_per_solve": a,
+            "achieved": round(a / t / 1e9, 1),
+            "frac": round(a / t / 1e9 / PEAK_HBM_GBS, 4),
+            "traffic_per_solve": meas,
+            "measured_hbm_GB/s": round(meas / t / 1e9, 1),
+            "measured_frac_of_hbm_peak": round(meas / t / 1e9 / PEAK_HBM_GBS, 4)}
     log(f"batched: {res}")
     del x, h, q, b
     T.tvs_ctx_destroy(ctx)

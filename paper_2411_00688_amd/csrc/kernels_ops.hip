@@ -1075,26 +1075,48 @@ __device__ __forceinline__ void rd_angle(int lane, int n_s, long long U, long lo
     }
 }
 
-// All angles of one class of the block's group for wavefront w (FULL: the
+// One angle of the block's group as the wavefronts read it: the lane-0 ray
+// position of each wavefront's strip (rd_entry) and its first ray's offset
+// in the staged window, the bin and step increments, and the angle's row of
+// the staged sinogram.  The records of a wavefront set are listed per class
+// in the order of the group's angles.
+struct RdRec {
+    long long K[4];
+    long long A, B;  // 32.32 increments per bin and per step
+    int bo[4];       // first ray of wavefront w minus the window start
+    int m;           // row of yS
+    int pad;
+};
+
+// All angles of one class of the wavefront set for wavefront w (FULL: the
 // strip has all RD_L steps, decided once for the loop so that the
-// accumulators stay in place from one angle to the next).
-template <int CLS, bool FULL>
-__device__ __forceinline__ void rd_class(const JAdjRdArgs<float>& a, const float (*yS)[RD_NB],
-                                         const int* wst, const int* ecls, const int (*eD)[4],
-                                         const long long (*eK)[4], int g, int G, int na_g,
-                                         int hf, int w, int lane, int n_s, float (&acc)[RD_L]) {
-    if (n_s <= 0) return;
-    for (int m = hf; m < na_g; m += RD_H) {
-        if (ecls[m] != CLS) continue;
-        const JAngle& gg = a.ang[g + m * G];
-        const int d0 = __builtin_amdgcn_readfirstlane(eD[m][w]);
-        const int ws = __builtin_amdgcn_readfirstlane(wst[m]);
-        const long long K = wave_uniform64(eK[m][w]);
-        int bi = d0 - ws + lane;
+// accumulators stay in place from one angle to the next).  The next angle's
+// record and sinogram value are read while the current angle's steps run.
+template <bool FULL>
+__device__ __forceinline__ void rd_class(const RdRec* rec, int cnt, const float (*yS)[RD_NB],
+                                         int w, int lane, int n_s, float (&acc)[RD_L]) {
+    if (n_s <= 0 || cnt <= 0) return;
+    auto fetch = [&](int k, long long& K, long long& A, long long& B, float& val) {
+        const RdRec& r = rec[k];
+        K = r.K[w];
+        A = r.A;
+        B = r.B;
+        int bi = r.bo[w] + lane;
         bi = bi < 0 ? 0 : (bi > RD_NB - 1 ? RD_NB - 1 : bi);
-        const float val = yS[m][bi];
-        const long long U = K + gg.Aqi * (long long)lane;
-        rd_angle<FULL>(lane, n_s, U, gg.Bqi, val, acc);
+        val = yS[r.m][bi];
+    };
+    long long K, A, B;
+    float val;
+    fetch(0, K, A, B, val);
+    for (int k = 0; k < cnt; ++k) {
+        long long Kn = K, An = A, Bn = B;
+        float valn = val;
+        if (k + 1 < cnt) fetch(k + 1, Kn, An, Bn, valn);
+        rd_angle<FULL>(lane, n_s, K + A * (long long)lane, B, val, acc);
+        K = Kn;
+        A = An;
+        B = Bn;
+        val = valn;
     }
 }
 
@@ -1112,10 +1134,11 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
     float (*tileT)[RD_P + 1] = sm.t.tileT;
     float (*rowS)[RD_P + 1] = sm.t.rowS;
     __shared__ int wst[RD_MAXA];
-    __shared__ int ecls[RD_MAXA];
     __shared__ float wgtS[RD_MAXA];
-    __shared__ int eD[RD_MAXA][4];
-    __shared__ long long eK[RD_MAXA][4];
+    __shared__ int lpos[RD_MAXA];        // an angle's place in its (set, class) list
+    __shared__ int lcnt[RD_H][2];        // list lengths
+    constexpr int RD_PER = (RD_MAXA + RD_H - 1) / RD_H;  // angles per set
+    __shared__ RdRec rec[RD_H][2][RD_PER];
     // block -> (angle group, tile), each XCD taking a contiguous range so that
     // the blocks sharing a group's sinogram rows share one L2
     const int tiles_x = div_up(a.W, RD_P), tiles = tiles_x * div_up(a.H, RD_P);
@@ -1127,15 +1150,42 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int w = wv & 3, hf = wv >> 2;
     const int na_g = (a.n_ang - g + G - 1) / G;
-    if (tid < na_g) {
-        const JAngle& gg = a.ang[g + tid * G];
-        wst[tid] = rd_window(gg, i0, j0);
-        ecls[tid] = gg.cls;
-        wgtS[tid] = (float)gg.wgt;
+    if (tid < 64) {
+        // wavefront 0, lane m = the group's angle m: window start, weight and
+        // the angle's place among the same set's angles of its class
+        const bool on = tid < na_g;
+        int cls = 0;
+        if (on) {
+            const JAngle& gg = a.ang[g + tid * G];
+            wst[tid] = rd_window(gg, i0, j0);
+            wgtS[tid] = (float)gg.wgt;
+            cls = gg.cls;
+        }
+        const unsigned long long below = (1ull << tid) - 1ull;
+#pragma unroll
+        for (int h = 0; h < RD_H; ++h)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const unsigned long long mk = __ballot(on && tid % RD_H == h && cls == c);
+                if (on && tid % RD_H == h && cls == c) lpos[tid] = __popcll(mk & below);
+                if (tid == 0) lcnt[h][c] = __popcll(mk);
+            }
     }
+    __syncthreads();
     if (tid < 4 * na_g) {
         const int m = tid >> 2, ww = tid & 3;
-        rd_entry(a.ang[g + m * G], i0, j0, ww, eD[m][ww], eK[m][ww]);
+        const JAngle& gg = a.ang[g + m * G];
+        RdRec& r = rec[m % RD_H][gg.cls][lpos[m]];
+        int d0;
+        long long K;
+        rd_entry(gg, i0, j0, ww, d0, K);
+        r.K[ww] = K;
+        r.bo[ww] = d0 - wst[m];
+        if (ww == 0) {
+            r.A = gg.Aqi;
+            r.B = gg.Bqi;
+            r.m = m;
+        }
     }
     __syncthreads();
     // the group's sinogram windows, RD_MAXA * RD_NB / RD_T loads per thread
@@ -1163,14 +1213,16 @@ __global__ __launch_bounds__(RD_T) void joseph_adj_rd_kernel(JAdjRdArgs<float> a
     for (int r = 0; r < RD_L; ++r) accR[r] = accC[r] = 0.0f;
     const int nR = __builtin_amdgcn_readfirstlane(a.H - (i0 + RD_L * w));
     const int nC = __builtin_amdgcn_readfirstlane(a.W - (j0 + RD_L * w));
+    const int cR = __builtin_amdgcn_readfirstlane(lcnt[hf][0]);
+    const int cC = __builtin_amdgcn_readfirstlane(lcnt[hf][1]);
     if (nR >= RD_L)
-        rd_class<0, true>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
+        rd_class<true>(rec[hf][0], cR, yS, w, lane, nR, accR);
     else
-        rd_class<0, false>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nR, accR);
+        rd_class<false>(rec[hf][0], cR, yS, w, lane, nR, accR);
     if (nC >= RD_L)
-        rd_class<1, true>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+        rd_class<true>(rec[hf][1], cC, yS, w, lane, nC, accC);
     else
-        rd_class<1, false>(a, yS, wst, ecls, eD, eK, g, G, na_g, hf, w, lane, nC, accC);
+        rd_class<false>(rec[hf][1], cC, yS, w, lane, nC, accC);
     __syncthreads();  // every wavefront is done with yS, which tileT and rowS overlay
     // Column-stepping sums are held per (column = 13 w + k, row = lane) and
     // are transposed through tileT.  The last set stores both its sums, the
