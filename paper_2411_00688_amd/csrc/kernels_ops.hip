@@ -576,64 +576,61 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
 // arithmetic per ray in the same order, so the sums equal
 // joseph_fwd_kernel's bit for bit.  The gather start is clamped into the
 // padded row [-JPAD, n_int], so every load stays inside the copy.
-// The steps of one pair of rays: ray a at Ua, ray b at Ua + dA (dA = the
-// bin step), both advancing by dB per step; NEG: ray b lies left of ray a.
-template <bool NEG>
-__device__ __forceinline__ void pair_walk(const char* img0, long long Ua, long long dA,
-                                          long long dB, int ro, int ld, int n_int, int n,
-                                          float& acc0a, float& acc1a, float& acc0b,
-                                          float& acc1b) {
-    long long Ub = Ua + dA;
-    int s = 0;
+// The steps of one pair of rays, tracked by the left one: UL its 32.32
+// position, the right ray at UL + D (D = |bin step| in [2^32, 2^33)), so the
+// right ray's fraction is the low word of UL plus that of D, and its pixel
+// pair starts 1 pixel further, or 2 when that addition carries.  Both
+// advance by dB per step.  rb: the lane's first row in bytes from img0 (pads
+// included); row k of the walk is rb + k ld4 bytes, k ld4 the same for every
+// lane.
+__device__ __forceinline__ void pair_walk(const char* img0, long long UL, unsigned Dlo,
+                                          long long dB, int rb, int ld4, int n_int, int n,
+                                          float& accL0, float& accL1, float& accR0,
+                                          float& accR1) {
+    int k = 0;
     // four gathers in flight before their sums
-    for (; s + 4 <= n; s += 4) {
+    for (; k + 4 <= n; k += 4) {
         float4 p[4];
-        unsigned fa[4], fb[4];
-        int j[4];
+        unsigned fl[4], fr[4];
+        bool two[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ha = (int)(Ua >> 32), hb = (int)(Ub >> 32);
-            int c = NEG ? hb : ha;
-            c = c < -JPAD ? -JPAD : (c > n_int ? n_int : c);  // stay inside the padded row
-            __builtin_memcpy(&p[k], img0 + ((unsigned)(ro + c) << 2), sizeof(float4));
-            fa[k] = (unsigned)Ua;
-            fb[k] = (unsigned)Ub;
-            j[k] = NEG ? ha - hb : hb - ha;  // the right ray's pair: 1 or 2 pixels further
-            Ua += dB;
-            Ub += dB;
-            ro += ld;
-            // one induction variable each (the compiler would otherwise keep
-            // a copy of each position per unrolled step)
-            __asm__("" : "+v"(Ua), "+v"(Ub));
+        for (int u = 0; u < 4; ++u) {
+            // gather start clamped into the padded row [-JPAD, n_int]
+            const int h = (int)(UL >> 32);
+            const int cc = max(-JPAD, min(h, n_int));
+            const char* row = img0 + (size_t)(k + u) * ld4;
+            __builtin_memcpy(&p[u], row + (unsigned)(rb + (cc << 2)), sizeof(float4));
+            fl[u] = (unsigned)UL;
+            fr[u] = fl[u] + Dlo;
+            two[u] = fr[u] < fl[u];  // the carry: right pair 2 pixels further
+            UL += dB;
+            // one induction variable (the compiler would otherwise keep a copy
+            // of the position per unrolled step)
+            __asm__("" : "+v"(UL));
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float q0 = j[k] == 1 ? p[k].y : p[k].z, q1 = j[k] == 1 ? p[k].z : p[k].w;
-            const float va0 = NEG ? q0 : p[k].x, va1 = NEG ? q1 : p[k].y;
-            const float vb0 = NEG ? p[k].x : q0, vb1 = NEG ? p[k].y : q1;
-            acc0a += va0;
-            acc1a = fmaf((float)fa[k], va1 - va0, acc1a);
-            acc0b += vb0;
-            acc1b = fmaf((float)fb[k], vb1 - vb0, acc1b);
+        for (int u = 0; u < 4; ++u) {
+            const float q0 = two[u] ? p[u].z : p[u].y, q1 = two[u] ? p[u].w : p[u].z;
+            accL0 += p[u].x;
+            accL1 = fmaf((float)fl[u], p[u].y - p[u].x, accL1);
+            accR0 += q0;
+            accR1 = fmaf((float)fr[u], q1 - q0, accR1);
         }
     }
-    for (; s < n; ++s) {
-        const int ha = (int)(Ua >> 32), hb = (int)(Ub >> 32);
-        int c = NEG ? hb : ha;
-        c = c < -JPAD ? -JPAD : (c > n_int ? n_int : c);
+    for (; k < n; ++k) {
+        const int h = (int)(UL >> 32);
+        const int cc = max(-JPAD, min(h, n_int));
+        const char* row = img0 + (size_t)k * ld4;
         float4 p;
-        __builtin_memcpy(&p, img0 + ((unsigned)(ro + c) << 2), sizeof(float4));
-        const int j = NEG ? ha - hb : hb - ha;
-        const float q0 = j == 1 ? p.y : p.z, q1 = j == 1 ? p.z : p.w;
-        const float va0 = NEG ? q0 : p.x, va1 = NEG ? q1 : p.y;
-        const float vb0 = NEG ? p.x : q0, vb1 = NEG ? p.y : q1;
-        acc0a += va0;
-        acc1a = fmaf((float)(unsigned)Ua, va1 - va0, acc1a);
-        acc0b += vb0;
-        acc1b = fmaf((float)(unsigned)Ub, vb1 - vb0, acc1b);
-        Ua += dB;
-        Ub += dB;
-        ro += ld;
+        __builtin_memcpy(&p, row + (unsigned)(rb + (cc << 2)), sizeof(float4));
+        const unsigned fl = (unsigned)UL, fr = fl + Dlo;
+        const bool two = fr < fl;
+        const float q0 = two ? p.z : p.y, q1 = two ? p.w : p.z;
+        accL0 += p.x;
+        accL1 = fmaf((float)fl, p.y - p.x, accL1);
+        accR0 += q0;
+        accR1 = fmaf((float)fr, q1 - q0, accR1);
+        UL += dB;
     }
 }
 
@@ -677,11 +674,14 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_pair_kernel(JFwdArgs<floa
         // from it and the clamped start in one instruction
         const long long Ua0 = g.Aqi * (long long)d0 + g.Cqi + g.Bqi * (long long)s_lo;
         const char* img0 = (const char*)(img - JPAD);
-        const int ro0 = s_lo * ld + JPAD;
+        const int rb = (s_lo * ld + JPAD) * 4;
+        // the left ray: a (A > 0) or b (A < 0)
+        const long long UL = neg ? Ua0 + g.Aqi : Ua0;
+        const unsigned Dlo = (unsigned)(neg ? -g.Aqi : g.Aqi);
         if (neg)
-            pair_walk<true>(img0, Ua0, g.Aqi, g.Bqi, ro0, ld, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
+            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi - s_lo, acc0b, acc1b, acc0a, acc1a);
         else
-            pair_walk<false>(img0, Ua0, g.Aqi, g.Bqi, ro0, ld, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
+            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
     }
     part[seg][2 * lane] = acc0a + acc1a * 2.3283064365386963e-10f;
     part[seg][2 * lane + 1] = acc0b + acc1b * 2.3283064365386963e-10f;
