@@ -1033,6 +1033,8 @@ def batched_bench(T, K=500, Kin=50, plain=True, tune_load=None, tune_save=None):
         res["fgp_roofline"] = {
             "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
             "profiled_solve_outer_iters": rec["outer_iters"],
+            "profiled_variant": rec["fgp_variant"],
+            "same_variant_as_this_run": rec["fgp_variant"] == list(T.tvs_fgp_variant(vb)),
             "kernel_ms_per_solve": rec["fgp_kernel_ms_per_solve"],
             "algorithmic_bytes_per_solve": a,
             "achieved": round(a / t / 1e9, 1),
