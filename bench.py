@@ -597,6 +597,7 @@ def fgp_hbm(T, ctx, n, Kin, resident=False):
         ms_fin = _evtime(lambda: T.tvs_tv_prox(ctx, v, 0.05, 0, 0, q, z), 3)
         ms = ms_all - ms_fin
         gbs = 28.0 * n * n * iters / (ms * 1e-3) / 1e9
+        log(f"  FGP {n}^2 variant {T.tvs_fgp_variant(vi)}: {ms / iters:.4f} ms per iteration")
         return {"variant": list(T.tvs_fgp_variant(vi)), "ms_per_iter": round(ms / iters, 4),
                 "GB/s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
 
