@@ -502,12 +502,15 @@ tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, 
  * tvs_solve_ext (NULL: the plain call):
  *  - cnn != NULL: every prox call of the run is the learned prox with the
  *    duality-gap gate of tvs_cnn_prox, decided on the device (so the run
- *    stays one HIP graph with TVS_FLAG_GRAPH): the network's dual P_lam(qt)
- *    becomes the call's dual when its relative gap is at most gap_tol;
- *    otherwise params->inner_iters FGP iterations run, warm-started from
- *    whichever of the network's dual and the previous call's dual (the warm
- *    dual the plain run reuses) has the smaller relative gap.  A NaN gap
- *    falls back.  float32 only (TVS_ERR_UNSUPPORTED else).
+ *    stays one HIP graph with TVS_FLAG_GRAPH).  The previous call's dual
+ *    (the warm dual the plain run reuses; zero at the first call unless the
+ *    state brings one) is checked first: when its relative gap at the new
+ *    prox input is at most gap_tol it is the call's dual, and neither the
+ *    network nor FGP runs.  Otherwise the network's dual P_lam(qt) becomes
+ *    the call's dual when its relative gap is at most gap_tol; else
+ *    params->inner_iters FGP iterations run, warm-started from whichever of
+ *    the two duals has the smaller relative gap.  A NaN gap falls back.
+ *    float32 only (TVS_ERR_UNSUPPORTED else).
  *  - v_record != NULL: the prox inputs v (the argument of the prox in
  *    Alg. "ProxSkip" / "PDHGSkip-2") of the first max_record prox calls are
  *    copied to v_record (device, dtype, max_record x H x W), the pairs that

@@ -108,7 +108,7 @@ static void pack_all(tvs_cnn* c) {
 // (hi + lo) BF16 operands; the activations' high parts always land in
 // B_X1..B_X3 (the backward pass reads them).
 static void forward_convs(tvs_cnn* c, int n, int H, int W, const float* v, float* qt_dst,
-                          int proj, bool split) {
+                          int proj, bool split, const int* run = nullptr) {
     const size_t npx = (size_t)n * H * W;
     const float* lam = (const float*)c->buf[tvs_cnn::B_LAM].ptr;
     uint16_t* x[3];
@@ -127,6 +127,7 @@ static void forward_convs(tvs_cnn* c, int n, int H, int W, const float* v, float
         a.wt = c->wf[l];
         a.wt_lo = c->wf_lo[l];
         a.bias = c->params + b_off(l);
+        a.run = run;
         if (l > 0) {
             a.in = x[l - 1];
             a.in_lo = xl[l - 1];
@@ -318,7 +319,7 @@ void prepare_solver_prox(tvs_cnn* c, int H, int W, double lam) {
     }
     scratch(c->ctx, S_Z, npx * sizeof(float));
     scratch(c->ctx, S_QNET, 2 * npx * sizeof(float));
-    scratch(c->ctx, S_SEL, sizeof(int));
+    scratch(c->ctx, S_SEL, 2 * sizeof(int));
     reserve_reduce_scratch(c->ctx, npx);
 }
 
@@ -327,26 +328,31 @@ float* enqueue_solver_prox(tvs_cnn* c, int H, int W, const float* v, double lam,
     tvs_ctx* ctx = c->ctx;
     const size_t npx = (size_t)H * W;
     float* qn = (float*)scratch(ctx, S_QNET, 2 * npx * sizeof(float));
-    forward_convs(c, 1, H, W, v, qn, 1, !c->fast);  // qn <- P_lam(qt)
+    float* z = (float*)scratch(ctx, S_Z, npx * sizeof(float));
     // relative duality gaps of the network's dual (red[0], red[1]) and of the
     // previous call's dual still in q (red[2], red[3])
-    float* z = (float*)scratch(ctx, S_Z, npx * sizeof(float));
     double* red = (double*)scratch(ctx, S_RED, 8 * sizeof(double));
-    float* cand[2] = {qn, q};
-    for (int i = 0; i < 2; ++i) {
+    int* sel = (int*)scratch(ctx, S_SEL, 2 * sizeof(int));
+    int* run = sel + 1;
+    auto gap_of = [&](float* cand, double* out) {
         Finalize<float> f{};
         f.v = v;
-        f.q = cand[i];
-        f.q_out = cand[i];
+        f.q = cand;
+        f.q_out = cand;
         f.z = z;
         f.nonneg = nonneg;
         f.mode = 0;
         launch_finalize<float>(ctx, H, W, f);
-        reduce_gap<float>(ctx, H, W, v, z, cand[i], lam, red + 2 * i, red + 2 * i + 1);
-    }
+        reduce_gap<float>(ctx, H, W, v, z, cand, lam, out, out + 1);
+    };
+    // the previous call's dual first: when it passes the gate it is the
+    // result and the network is not evaluated (its kernels return at once)
+    gap_of(q, red + 2);
+    launch_pregate(ctx, red, tol, run);
+    forward_convs(c, 1, H, W, v, qn, 1, !c->fast, run);  // qn <- P_lam(qt)
+    gap_of(qn, red);  // not read by the gate when the network was skipped
     int* flag = record;  // the per-call record doubles as this call's flag
-    int* sel = (int*)scratch(ctx, S_SEL, sizeof(int));
-    launch_gate(ctx, red, tol, flag, sel);
+    launch_gate(ctx, red, tol, run, flag, sel);
     launch_copy_if(ctx, 2 * npx, sel, 1, qn, q);  // start (or result): the network's dual
     float* qf = run_fgp<float>(ctx, H, W, v, lam, iters, nonneg, q, cfg, flag);
     if (qf != q) launch_copy_if(ctx, 2 * npx, flag, 0, q, qf);

@@ -60,6 +60,7 @@ __device__ __forceinline__ float ball_scale_f(float wy, float wx, float lam) {
 // product error near 2^-16 instead of 2^-8.
 template <int CIN, int COUTP, int IN, int OUT, bool SPLIT>
 __global__ __launch_bounds__(SPLIT ? 512 : 256) void conv3x3_kernel(ConvArgs a) {
+    if (a.run && *a.run == 0) return;  // the gate has already decided this call
     constexpr int NT = SPLIT ? 512 : 256;
     constexpr int NW = NT / 64;
     constexpr int RPW = CONV_TILE / NW;            // output rows per wave
@@ -565,14 +566,28 @@ __global__ void pack_weights_kernel(const float* w, int cin, int cout, int coutp
 // ------------------------------------------------------------------ gate
 // Gate of a learned prox call inside a solver run.  red[0], red[1]: gap and
 // primal value at the network's dual; red[2], red[3]: the same at the
-// previous call's dual.  flag = 0 when the network's relative gap is at most
-// tol (its dual is the result), else 1 (FGP runs; a NaN gap falls back too).
-// sel = 1 when the network's dual is the result or FGP's start: gate open,
-// or a relative gap below the previous dual's.
-__global__ void gate_kernel(const double* red, double tol, int* flag, int* sel) {
+// previous call's dual.
+// pregate: run = 0 when the previous dual's relative gap is at most tol
+// (it is the call's result; the network is not evaluated), else 1.
+// gate: with run = 0, flag = 0 and sel = 0.  Otherwise flag = 0 when the
+// network's relative gap is at most tol (its dual is the result), else 1
+// (FGP runs; a NaN gap falls back too); sel = 1 when the network's dual is
+// the result or FGP's start: gate open, or a relative gap below the
+// previous dual's.
+__device__ __forceinline__ double rel_gap(const double* r) { return r[1] > 0.0 ? r[0] / r[1] : r[0]; }
+
+__global__ void pregate_kernel(const double* red, double tol, int* run) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) run[0] = rel_gap(red + 2) <= tol ? 0 : 1;
+}
+
+__global__ void gate_kernel(const double* red, double tol, const int* run, int* flag, int* sel) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const double rn = red[1] > 0.0 ? red[0] / red[1] : red[0];
-        const double rp = red[3] > 0.0 ? red[2] / red[3] : red[2];
+        if (run && run[0] == 0) {
+            flag[0] = 0;
+            sel[0] = 0;
+            return;
+        }
+        const double rn = rel_gap(red), rp = rel_gap(red + 2);
         const int f = rn <= tol ? 0 : 1;
         flag[0] = f;
         sel[0] = (f == 0 || rn < rp) ? 1 : 0;
@@ -704,8 +719,13 @@ void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, 
     TVS_LAUNCH_CHECK();
 }
 
-void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* sel) {
-    gate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, flag, sel);
+void launch_pregate(tvs_ctx* ctx, const double* red, double tol, int* run) {
+    pregate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, run);
+    TVS_LAUNCH_CHECK();
+}
+
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, const int* run, int* flag, int* sel) {
+    gate_kernel<<<1, 64, 0, ctx->stream>>>(red, tol, run, flag, sel);
     TVS_LAUNCH_CHECK();
 }
 

@@ -415,6 +415,7 @@ struct ConvArgs {
     float* out_f = nullptr;         // OUT_F32_PLANAR: [n][2][H][W]
     int proj = 0;                   // OUT_F32_PLANAR: project onto the lam ball
     int tiles_x = 0, tiles_y = 0, n_tiles = 0;
+    const int* run = nullptr;       // device flag (nullable): 0 = return at once
 };
 struct WgradArgs {
     int n = 0, H = 0, W = 0;
@@ -451,7 +452,8 @@ void launch_adam(tvs_ctx* ctx, int n, float* p, const float* grad, float* m, flo
                  float b1, float b2, float c1, float c2, float eps);
 void launch_pack(tvs_ctx* ctx, const float* w, int cin, int cout, uint16_t* wf, uint16_t* wf_lo,
                  uint16_t* wb);
-void launch_gate(tvs_ctx* ctx, const double* red, double tol, int* flag, int* sel);
+void launch_pregate(tvs_ctx* ctx, const double* red, double tol, int* run);
+void launch_gate(tvs_ctx* ctx, const double* red, double tol, const int* run, int* flag, int* sel);
 void launch_copy_if(tvs_ctx* ctx, size_t n, const int* flag, int when, const float* src,
                     float* dst);
 // Learned prox inside a solver run (capturable): allocations and lam set up

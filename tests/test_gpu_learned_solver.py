@@ -11,6 +11,10 @@ recording (tvs_proxskip_ex / tvs_pdhgskip_ex).
   from the zero network dual or the previous call's dual, whichever has the
   smaller relative gap: the run equals the oracle stepped one iteration at a
   time with that choice made in float64 before each prox call.
+- The previous call's dual is checked before the network: a network whose
+  output is NaN never matters when that dual passes the gate (no call falls
+  back, the run equals the alpha = 0 run), and always falls back when it
+  does not (the run equals the plain run).
 """
 import numpy as np
 import pytest
@@ -138,10 +142,10 @@ def test_zero_network_gate_closed_starts_from_better_dual(ctx, zero_cnn):
 def test_nan_network_always_falls_back(ctx):
     """A network whose float32 activations overflow (all parameters 1e30, as
     after diverged training) yields NaN duals (inf scaled by 0 in the ball
-    projection) and a NaN gap: every call falls back, inside a solver run
-    from the previous call's dual, so the run equals the plain run bit for
-    bit (graph and stream), and the standalone prox runs FGP from the zero
-    dual."""
+    projection) and a NaN gap: with a gate no previous dual passes, every
+    call falls back, inside a solver run from the previous call's dual, so
+    the run equals the plain run bit for bit (graph and stream), and the
+    standalone prox runs FGP from the zero dual."""
     cnn = T.tvs_cnn_create(ctx, 1)
     T.tvs_cnn_set_params(cnn, np.full(T.tvs_cnn_param_count(), 1e30, dtype=np.float32))
     A, b, L, op = ct_setup(ctx)
@@ -154,7 +158,7 @@ def test_nan_network_always_falls_back(ctx):
         for graph in (False, True):
             st = [zeros((N, N)), zeros((N, N)), zeros((2, N, N)), zeros((na, nd))]
             r = T.tvs_pdhgskip_ex(op, dev(b, F32), *st, 0.05, 1 / L, 1 / L, p, K, Kin, nonneg=1,
-                                  seed=seed, graph=graph, cnn=cnn, gap_tol=1.0)
+                                  seed=seed, graph=graph, cnn=cnn, gap_tol=1e-12)
             assert r["n_fallback"] == r["n_prox"] == r0["n_prox"] > 0
             for k in range(4):
                 assert torch.equal(st[k], ref[k]), (graph, k)
@@ -166,6 +170,32 @@ def test_nan_network_always_falls_back(ctx):
         q0, z0 = zeros((2, N, N)), torch.empty(N, N, dtype=F32, device="cuda")
         T.tvs_tv_prox(ctx, v, 0.2, 15, 1, q0, z0)
         assert torch.equal(q, q0) and torch.equal(z, z0)
+    finally:
+        T.tvs_op_destroy(op)
+        T.tvs_cnn_destroy(cnn)
+
+
+def test_previous_dual_that_passes_the_gate_skips_the_network(ctx):
+    """Gate 1: the zero dual of the first call passes (its relative gap,
+    TV(z) lam / P(z), is at most 1), so does every later call's (still zero):
+    the NaN network is never consulted, no call falls back, and the run
+    equals the alpha = 0 run (z = P_X(v) at every call) bit for bit."""
+    cnn = T.tvs_cnn_create(ctx, 1)
+    T.tvs_cnn_set_params(cnn, np.full(T.tvs_cnn_param_count(), 1e30, dtype=np.float32))
+    A, b, L, op = ct_setup(ctx)
+    N, (na, nd) = A.H, A.out_shape
+    K, Kin, p, seed = 40, 10, 0.3, 12
+    try:
+        ref = [zeros((N, N)), zeros((N, N)), zeros((2, N, N)), zeros((na, nd))]
+        T.tvs_pdhgskip(op, dev(b, F32), *ref, 0.0, 1 / L, 1 / L, p, K, Kin, nonneg=1, seed=seed)
+        for graph in (False, True):
+            st = [zeros((N, N)), zeros((N, N)), zeros((2, N, N)), zeros((na, nd))]
+            r = T.tvs_pdhgskip_ex(op, dev(b, F32), *st, 0.05, 1 / L, 1 / L, p, K, Kin, nonneg=1,
+                                  seed=seed, graph=graph, cnn=cnn, gap_tol=1.0)
+            assert r["n_prox"] > 0 and r["n_fallback"] == 0
+            for k in (0, 1, 3):
+                assert torch.equal(st[k], ref[k]), (graph, k)
+            assert torch.count_nonzero(st[2]) == 0
     finally:
         T.tvs_op_destroy(op)
         T.tvs_cnn_destroy(cnn)
