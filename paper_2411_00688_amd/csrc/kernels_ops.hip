@@ -19,10 +19,10 @@
 
 namespace tvs {
 
+// The step with x = ps.x[g] and hh = ps.h[g] already loaded.
 template <typename T>
-__device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, int i, int j, T s) {
-    const T x = ps.x[g];
-    const T hh = ps.h[g];
+__device__ __forceinline__ T primal_step_xh(const PrimalStep<T>& ps, size_t g, int i, int j, T s,
+                                            T x, T hh) {
     const T w = x - ps.step * s;
     const T xh = w + ps.step * hh;
     if (ps.theta) {
@@ -37,6 +37,11 @@ __device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, int 
         return xb;
     }
     return T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T primal_step(const PrimalStep<T>& ps, size_t g, int i, int j, T s) {
+    return primal_step_xh(ps, g, i, j, s, ps.x[g], ps.h[g]);
 }
 
 // z += s; zbar = z + nsub s (the stochastic-angle method's dual sums).
@@ -1278,20 +1283,29 @@ __global__ __launch_bounds__(1024) void joseph_adj_sum_kernel(const T* part, int
     const int i = i0 + li, j = j0 + lj;
     if (i < H && j < W) {
         const size_t gi = (size_t)i * W + j;
+        // the data step's own operands are loaded with the partials, so that
+        // all of them are in flight together
+        T xo = T(0), ho = T(0);
+        if (has_ps) {
+            xo = ps.x[gi];
+            ho = ps.h[gi];
+        }
         T s = part[gi];
         // partials 1 .. G-1 in order, eight loads in flight at a time (a
-        // plain loop over the runtime G waits for each load before the next)
+        // plain loop over the runtime G waits for each load before the
+        // next); indices clamped to the last partial, so no branch guards a
+        // load, and only the partials below G are added
         for (int k = 1; k < G; k += 8) {
             T v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                v[u] = (k + u < G) ? part[(size_t)(k + u) * plane + gi] : T(0);
+                v[u] = part[(size_t)(k + u < G ? k + u : G - 1) * plane + gi];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (k + u < G) s += v[u];
         }
         if (has_ps)
-            s_t[li][lj] = primal_step(ps, gi, i, j, s);
+            s_t[li][lj] = primal_step_xh(ps, gi, i, j, s, xo, ho);
         else if (has_za)
             z_accumulate(za, gi, s);
         else
