@@ -214,10 +214,28 @@ void autotune_batched(tvs_ctx* ctx, int n, const tvs_slice* S, int iters, int re
             return p;
         }
     } tmp;
+    // The slices a prox call of the run actually covers: those whose coin is
+    // 1 at each of the first kProbe outer iterations (k0 = 0), so that the
+    // variant is chosen for the active sets the solve will see (a fraction p
+    // of the slices), not for all slices at once.  With no active slice in
+    // those iterations, every slice.
+    constexpr int kProbe = 8;
+    std::vector<std::vector<int>> sets;
+    for (int k = 0; k < kProbe; ++k) {
+        std::vector<int> a;
+        for (int s = 0; s < n; ++s)
+            if (coin(S[s].seed, S[s].stream_id, k, S[s].p) == 1) a.push_back(s);
+        if (!a.empty()) sets.push_back(std::move(a));
+    }
+    if (sets.empty()) {
+        sets.emplace_back();
+        for (int s = 0; s < n; ++s) sets.back().push_back(s);
+    }
+    const int n_sets = (int)sets.size();
     T* v = (T*)tmp.alloc(total * sizeof(T));
     T* q = (T*)tmp.alloc(2 * total * sizeof(T));
     BSlice<T>* d_sl = (BSlice<T>*)tmp.alloc(n * sizeof(BSlice<T>));
-    int* d_list = (int*)tmp.alloc((size_t)(3 * n + 2) * sizeof(int));
+    int* d_list = (int*)tmp.alloc((size_t)n_sets * (3 * n + 2) * sizeof(int));
     TVS_HIP(hipMemcpy(v, hv.data(), total * sizeof(T), hipMemcpyHostToDevice));
     TVS_HIP(hipMemcpy(d_sl, hs.data(), n * sizeof(BSlice<T>), hipMemcpyHostToDevice));
     TVS_HIP(hipEventCreate(&tmp.e0));
@@ -234,31 +252,40 @@ void autotune_batched(tvs_ctx* ctx, int n, const tvs_slice* S, int iters, int re
             if (ms_out) ms_out[vi] = -1.0;
             continue;
         }
-        // work lists with every slice active: act, FGP tile prefix, 32 x 32 prefix
-        std::vector<int> ints;
-        for (int s = 0; s < n; ++s) ints.push_back(s);
-        int cf = 0, cn = 0;
-        ints.push_back(0);
-        for (int s = 0; s < n; ++s) ints.push_back(cf += tiles_of(S[s].H, S[s].W, c.tile_w, c.tile_h));
-        ints.push_back(0);
-        for (int s = 0; s < n; ++s) ints.push_back(cn += tiles_of(S[s].H, S[s].W, 32, 32));
+        // one work list per active set: act, FGP tile prefix, 32 x 32 prefix
+        std::vector<BatchLists> Ls(n_sets);
+        std::vector<int> ints((size_t)n_sets * (3 * n + 2), 0);
+        for (int j = 0; j < n_sets; ++j) {
+            const std::vector<int>& a = sets[j];
+            const int na = (int)a.size();
+            int* li = ints.data() + (size_t)j * (3 * n + 2);
+            int cf = 0, cn = 0;
+            for (int t = 0; t < na; ++t) li[t] = a[t];
+            li[na] = 0;
+            for (int t = 0; t < na; ++t)
+                li[na + 1 + t] = cf += tiles_of(S[a[t]].H, S[a[t]].W, c.tile_w, c.tile_h);
+            li[2 * na + 1] = 0;
+            for (int t = 0; t < na; ++t) li[2 * na + 2 + t] = cn += tiles_of(S[a[t]].H, S[a[t]].W, 32, 32);
+            int* dl = d_list + (size_t)j * (3 * n + 2);
+            Ls[j].n_act = na;
+            Ls[j].act = dl;
+            Ls[j].pref_fgp = dl + na;
+            Ls[j].pref_fin = dl + 2 * na + 1;
+            Ls[j].tiles_fgp = cf;
+            Ls[j].tiles_fin = cn;
+        }
         TVS_HIP(hipMemcpy(d_list, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice));
-        BatchLists L;
-        L.n_act = n;
-        L.act = d_list;
-        L.pref_fgp = d_list + n;
-        L.pref_fin = d_list + 2 * n + 1;
-        L.tiles_fgp = cf;
-        L.tiles_fin = cn;
         launch_fill<T>(ctx, 2 * total, T(0), q);
-        run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);  // warm-up
+        for (const BatchLists& L : Ls) run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);  // warm-up
         TVS_HIP(hipEventRecord(tmp.e0, ctx->stream));
-        for (int r = 0; r < reps; ++r) run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);
+        for (int r = 0; r < reps; ++r)
+            for (const BatchLists& L : Ls) run_fgp_batched<T>(ctx, d_sl, L, v, q, total, iters, 0, c);
         TVS_HIP(hipEventRecord(tmp.e1, ctx->stream));
         TVS_HIP(hipEventSynchronize(tmp.e1));
         float ms = 0;
         TVS_HIP(hipEventElapsedTime(&ms, tmp.e0, tmp.e1));
-        const double per_iter = (double)ms / ((double)reps * iters);
+        // time per FGP iteration of one prox call of the run (an average active set)
+        const double per_iter = (double)ms / ((double)reps * iters * n_sets);
         if (ms_out) ms_out[vi] = per_iter;
         if (per_iter < best_ms) {
             best_ms = per_iter;
