@@ -581,6 +581,22 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_kernel(JFwdArgs<T> a) {
 // arithmetic per ray in the same order, so the sums equal
 // joseph_fwd_kernel's bit for bit.  The gather start is clamped into the
 // padded row [-JPAD, n_int], so every load stays inside the copy.
+// med3(x, lo, hi) in one instruction (lo <= hi is the caller's to ensure;
+// the compiler emits a min and a max when it cannot prove it)
+__device__ __forceinline__ int clamp_med3(int x, int lo, int hi) {
+    int r;
+    __asm__("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "s"(hi));
+    return r;
+}
+
+// base + 4 x in one instruction (left to itself the compiler refactors the
+// sum around the row base and spends two)
+__device__ __forceinline__ unsigned byte_off4(int x, unsigned base) {
+    unsigned r;
+    __asm__("v_lshl_add_u32 %0, %1, 2, %2" : "=v"(r) : "v"(x), "v"(base));
+    return r;
+}
+
 // The steps of one pair of rays, tracked by the left one: UL its 32.32
 // position, the right ray at UL + D (D = |bin step| in [2^32, 2^33)), so the
 // right ray's fraction is the low word of UL plus that of D, and its pixel
@@ -602,9 +618,9 @@ __device__ __forceinline__ void pair_walk(const char* img0, long long UL, unsign
         for (int u = 0; u < 4; ++u) {
             // gather start clamped into the padded row [-JPAD, n_int]
             const int h = (int)(UL >> 32);
-            const int cc = max(-JPAD, min(h, n_int));
+            const int cc = clamp_med3(h, -JPAD, n_int);  // n_int >= 1 > -JPAD
             const char* row = img0 + (size_t)(k + u) * ld4;
-            __builtin_memcpy(&p[u], row + (unsigned)(rb + (cc << 2)), sizeof(float4));
+            __builtin_memcpy(&p[u], row + byte_off4(cc, (unsigned)rb), sizeof(float4));
             fl[u] = (unsigned)UL;
             fr[u] = fl[u] + Dlo;
             two[u] = fr[u] < fl[u];  // the carry: right pair 2 pixels further
@@ -624,10 +640,10 @@ __device__ __forceinline__ void pair_walk(const char* img0, long long UL, unsign
     }
     for (; k < n; ++k) {
         const int h = (int)(UL >> 32);
-        const int cc = max(-JPAD, min(h, n_int));
+        const int cc = clamp_med3(h, -JPAD, n_int);  // n_int >= 1 > -JPAD
         const char* row = img0 + (size_t)k * ld4;
         float4 p;
-        __builtin_memcpy(&p, row + (unsigned)(rb + (cc << 2)), sizeof(float4));
+        __builtin_memcpy(&p, row + byte_off4(cc, (unsigned)rb), sizeof(float4));
         const unsigned fl = (unsigned)UL, fr = fl + Dlo;
         const bool two = fr < fl;
         const float q0 = two ? p.z : p.y, q1 = two ? p.w : p.z;
