@@ -669,13 +669,15 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_pair_kernel(JFwdArgs<floa
     const int s0 = (seg * n_step) / SEG, s1 = ((seg + 1) * n_step) / SEG;
     const bool neg = g.A < 0.0;  // wave-uniform: which ray of the pair lies left
     float acc0a = 0.0f, acc1a = 0.0f, acc0b = 0.0f, acc1b = 0.0f;
+    int lo = s1, hi = s0;  // no steps for lanes past the detector
     if (d0 < a.n_det) {
         // steps where either ray's sample can touch the image: with
         // u_a = A d0 + B s + C and u_b = u_a + A, the union of -1 <= u < n_int
         // over both is -1 - max(A, 0) <= u_a < n_int - min(A, 0)
         const double base = fma(g.A, (double)d0, g.C);
         const double ulo = -1.0 - (g.A > 0.0 ? g.A : 0.0), uhi = (double)n_int - (g.A < 0.0 ? g.A : 0.0);
-        int lo = s0, hi = s1;
+        lo = s0;
+        hi = s1;
         if (g.B != 0.0) {
             double t1 = (ulo - base) / g.B, t2 = (uhi - base) / g.B;
             double tmin = t1 < t2 ? t1 : t2, tmax = t1 < t2 ? t2 : t1;
@@ -688,11 +690,25 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_pair_kernel(JFwdArgs<floa
         } else if (!(base >= ulo && base < uhi)) {
             hi = lo;
         }
-        const int s_lo = lo > 0 ? lo : 0;
+    }
+    // The wavefront walks the union of its lanes' step ranges, every lane on
+    // the same row at each step (its 64 gathers then share a few cache
+    // lines).  Outside a lane's own range both of its samples lie outside
+    // [-1, n_int), so the gathered pixels are pads and add exact zeros.
+    int lo_w = lo, hi_w = hi;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo_w = min(lo_w, __shfl_xor(lo_w, o));
+        hi_w = max(hi_w, __shfl_xor(hi_w, o));
+    }
+    lo_w = __builtin_amdgcn_readfirstlane(lo_w);
+    hi_w = __builtin_amdgcn_readfirstlane(hi_w);
+    if (hi_w > lo_w) {
+        const int s_lo = lo_w;  // >= s0 >= 0
         // 32.32 positions of both rays relative to their row; the row's
-        // element offset in the padded copy (pads included) advances
-        // separately, and a gather's byte offset (within 4 GiB) is formed
-        // from it and the clamped start in one instruction
+        // byte offset in the padded copy (pads included) is the same for
+        // every lane, and a gather's offset is formed from it and the
+        // clamped start in one instruction
         const long long Ua0 = g.Aqi * (long long)d0 + g.Cqi + g.Bqi * (long long)s_lo;
         const char* img0 = (const char*)(img - JPAD);
         const int rb = (s_lo * ld + JPAD) * 4;
@@ -700,9 +716,9 @@ __global__ __launch_bounds__(64 * SEG) void joseph_fwd_pair_kernel(JFwdArgs<floa
         const long long UL = neg ? Ua0 + g.Aqi : Ua0;
         const unsigned Dlo = (unsigned)(neg ? -g.Aqi : g.Aqi);
         if (neg)
-            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi - s_lo, acc0b, acc1b, acc0a, acc1a);
+            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi_w - s_lo, acc0b, acc1b, acc0a, acc1a);
         else
-            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi - s_lo, acc0a, acc1a, acc0b, acc1b);
+            pair_walk(img0, UL, Dlo, g.Bqi, rb, ld * 4, n_int, hi_w - s_lo, acc0a, acc1a, acc0b, acc1b);
     }
     part[seg][2 * lane] = acc0a + acc1a * 2.3283064365386963e-10f;
     part[seg][2 * lane + 1] = acc0b + acc1b * 2.3283064365386963e-10f;
