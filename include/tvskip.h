@@ -412,9 +412,12 @@ tvs_status tvs_proxskip_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
 /* FGP tile variant used by tvs_proxskip_batched for batches of n_slices
  * slices in this context (-1 restores the default). */
 tvs_status tvs_fgp_set_variant_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices, int index);
-/* Times every FGP variant on one FGP pass over a batch with these slice
- * sizes and parameters (all slices active, seeded random data on private
- * pools; offsets are ignored), keeps the fastest for n_slices slices.
+/* Times every FGP variant on the FGP passes a run of these slices makes at
+ * its first 8 outer iterations (k0 = 0): each pass covers the slices whose
+ * coin (seed, stream_id, p) is 1 at that iteration, or every slice when
+ * none is; seeded random data on private pools, offsets ignored.  Keeps the
+ * fastest for n_slices slices; ms_per_iter_out gets each variant's time per
+ * FGP iteration of one such pass (-1 if not compiled for the dtype).
  * Outputs as tvs_fgp_autotune. */
 tvs_status tvs_fgp_autotune_batched(tvs_ctx* ctx, tvs_dtype dtype, int n_slices,
                                     const tvs_slice* slices, int inner_iters, int reps,

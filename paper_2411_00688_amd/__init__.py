@@ -477,7 +477,8 @@ def tvs_fgp_set_variant_batched(ctx: int, dtype: int, n_slices: int, index: int)
 
 
 def tvs_fgp_autotune_batched(ctx: int, dtype: int, slices, inner_iters: int = 50, reps: int = 2):
-    """Times every FGP variant on one pass over a batch of these slices; keeps
+    """Times every FGP variant on the passes a run of these slices makes at
+    its first 8 outer iterations (the slices whose coin is 1 there); keeps
     the fastest for len(slices) slices.  Returns (best_index, [ms per iter])."""
     import numpy as np
     ms = np.zeros(tvs_fgp_variant_count())
