@@ -175,8 +175,11 @@ using namespace tvs;
 
 namespace {
 
-// Small images use 16 x 16 tiles so that the launch still fills the GPU.
-constexpr int LP_TS = 8;
+// Small images use 16 x 16 tiles with 8 steps per launch so that the launch
+// still fills the GPU; large ones 32 x 32 tiles with 6 steps (40 x 40
+// regions instead of 48 x 48: the halo recomputation, which bounds the
+// kernel, shrinks faster than the extra launches' traffic grows).
+constexpr int LP_TS_SMALL = 8, LP_TS_BIG = 6;
 
 template <typename T>
 void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
@@ -198,8 +201,9 @@ void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
     const T* qi = q;
     const T* hi = h;
     bool in_caller = true;
-    for (int64_t k = 0; k < P->outer_iters; k += LP_TS) {
-        const int ns = (int)std::min<int64_t>(LP_TS, P->outer_iters - k);
+    const int ts = big ? LP_TS_BIG : LP_TS_SMALL;
+    for (int64_t k = 0; k < P->outer_iters; k += ts) {
+        const int ns = (int)std::min<int64_t>(ts, P->outer_iters - k);
         unsigned mask = 0;
         for (int s = 0; s < ns; ++s) mask |= (unsigned)theta[(size_t)(k + s)] << s;
         a.q = qi;
@@ -209,9 +213,9 @@ void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
         a.nsteps = ns;
         a.theta = mask;
         if (big)
-            launch_lp<T, 32, 32, LP_TS>(a, ctx->stream);
+            launch_lp<T, 32, 32, LP_TS_BIG>(a, ctx->stream);
         else
-            launch_lp<T, 16, 16, LP_TS>(a, ctx->stream);
+            launch_lp<T, 16, 16, LP_TS_SMALL>(a, ctx->stream);
         TVS_LAUNCH_CHECK();
         qi = a.qo;
         hi = a.ho;
