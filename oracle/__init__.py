@@ -127,6 +127,16 @@ def lib():
         L.orc_dual_rof_proxskip.restype = C.c_int64
         L.orc_dual_rof_projgd.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double,
                                           C.c_double, C.c_int64, dp]
+        L.orc_tv_prox_skip.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_int,
+                                       C.c_double, C.c_uint64, C.c_uint64, C.c_int64, dp, dp, dp]
+        L.orc_tv_prox_skip.restype = C.c_int64
+        i64p = C.POINTER(C.c_int64)
+        L.orc_proxskip_inner.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, dp, C.c_double,
+                                         C.POINTER(OrcParams), u8p, dp, i64p]
+        L.orc_proxskip_inner.restype = C.c_int64
+        L.orc_pdhgskip_inner.argtypes = [C.POINTER(OrcOp), dp, dp, dp, dp, dp, dp, C.c_double,
+                                         C.POINTER(OrcParams), u8p, dp, i64p]
+        L.orc_pdhgskip_inner.restype = C.c_int64
         L.orc_cnn_param_count.argtypes = []
         L.orc_cnn_param_count.restype = C.c_size_t
         L.orc_cnn_forward.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp, dp]
@@ -438,6 +448,63 @@ def dual_rof_projgd(b, alpha, eps, gamma, K, q=None):
     q = _state(q, (2, H, W))
     lib().orc_dual_rof_projgd(H, W, _p(b), float(alpha), float(eps), float(gamma), int(K), _p(q))
     return dict(q=q, u=b + div(q))
+
+
+# ---------------------------------------------------------------- inner-solver skip
+INNER_STREAM = 1 << 62
+
+
+def tv_prox_skip(v, lam, iters, p_in, nonneg=0, seed=0, stream=0, k0=0, q=None, h=None):
+    """TV prox by ProxSkip on its dual (step 1/8).  Returns dict(z, q, h, nproj)."""
+    v = _f64(v)
+    H, W = v.shape
+    q = _state(q, (2, H, W))
+    h = _state(h, (2, H, W))
+    z = np.zeros((H, W))
+    n = lib().orc_tv_prox_skip(H, W, _p(v), float(lam), int(nonneg), int(iters), float(p_in),
+                               int(seed), int(stream), int(k0), _p(q), _p(h), _p(z))
+    return dict(z=z, q=q, h=h, nproj=int(n))
+
+
+def proxskip_inner(A: Op, b, alpha, step, p, outer, inner, p_in, nonneg=0, seed=0, stream=0,
+                   k0=0, x=None, h=None, q=None, h_in=None, want_obj=False):
+    """ProxSkip with the TV prox by tv_prox_skip.  Returns dict(x, h, q, h_in, theta,
+    obj, nprox, nproj)."""
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, h = _state(x, (H, W)), _state(h, (H, W))
+    q, h_in = _state(q, (2, H, W)), _state(h_in, (2, H, W))
+    theta = np.zeros(outer, dtype=np.uint8)
+    obj = np.zeros(outer) if want_obj else None
+    nproj = C.c_int64(0)
+    P = _params(alpha, step, 0.0, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_proxskip_inner(C.byref(A.s), _p(b), _p(x), _p(h), _p(q), _p(h_in),
+                                 float(p_in), C.byref(P),
+                                 theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 _p(obj) if want_obj else None, C.byref(nproj))
+    return dict(x=x, h=h, q=q, h_in=h_in, theta=theta, obj=obj, nprox=int(n),
+                nproj=int(nproj.value))
+
+
+def pdhgskip_inner(A: Op, b, alpha, sigma, tau, p, outer, inner, p_in, nonneg=0, seed=0,
+                   stream=0, k0=0, x=None, h=None, y=None, q=None, h_in=None, want_obj=False):
+    """PDHGSkip-2 with the TV prox by tv_prox_skip.  Returns dict(x, h, y, q, h_in,
+    theta, obj, nprox, nproj)."""
+    b = _f64(b)
+    H, W = A.H, A.W
+    x, h = _state(x, (H, W)), _state(h, (H, W))
+    q, h_in = _state(q, (2, H, W)), _state(h_in, (2, H, W))
+    y = _state(y, A.out_shape)
+    theta = np.zeros(outer, dtype=np.uint8)
+    obj = np.zeros(outer) if want_obj else None
+    nproj = C.c_int64(0)
+    P = _params(alpha, sigma, tau, p, outer, inner, nonneg, seed, stream, k0)
+    n = lib().orc_pdhgskip_inner(C.byref(A.s), _p(b), _p(x), _p(h), _p(y), _p(q), _p(h_in),
+                                 float(p_in), C.byref(P),
+                                 theta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 _p(obj) if want_obj else None, C.byref(nproj))
+    return dict(x=x, h=h, y=y, q=q, h_in=h_in, theta=theta, obj=obj, nprox=int(n),
+                nproj=int(nproj.value))
 
 
 # ---------------------------------------------------------------- learned prox

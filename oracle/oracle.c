@@ -923,3 +923,162 @@ void orc_dual_rof_projgd(int H, int W, const double* b, double alpha, double eps
     }
     free(u); free(g); free(t);
 }
+
+/* ------------------------------------------------------------------------
+ * Skipping inside the inner solver (the paper's "Discussion and Future
+ * work"): the TV prox z = argmin 1/2 |z - v|^2 + lam TV(z) (+ z >= 0) solved
+ * by ProxSkip on its dual instead of FGP.  The dual (Sec. 2.1; with z >= 0
+ * the constrained dual of Beck and Teboulle 2009) is
+ *   min_{|q_i| <= lam} F(q),  grad F(q) = -D P_X(v + div q),
+ * P_X = max(., 0) when nonneg, else the identity (then F is the Dual-ROF
+ * objective 1/2 |v + div q|^2); its nonsmooth part is the indicator of the
+ * lam-ball, whose prox is the projection of eq. (7).  ProxSkip (Alg.
+ * "ProxSkip") with step 1/8 (|D|^2 <= 8, the step FGP takes) and
+ * projection probability p_in, from the warm (q, h); z = P_X(v + div q).
+ * The coin of inner step i is orc_coin(seed, stream, k0 + i, p_in).
+ * Returns the number of projections.
+ * ------------------------------------------------------------------------ */
+int64_t orc_tv_prox_skip(int H, int W, const double* v, double lam, int nonneg, int iters,
+                         double p_in, uint64_t seed, uint64_t stream, int64_t k0, double* q,
+                         double* h, double* z_out) {
+    size_t n = (size_t)H * W;
+    const double gamma = 0.125, coef = gamma - gamma / p_in, rate = p_in / gamma;
+    double* u = dalloc(n);
+    double* g = dalloc(2 * n);
+    double* qhat = dalloc(2 * n);
+    double* w2 = dalloc(2 * n);
+    int64_t nproj = 0;
+    for (int it = 0; it < iters; ++it) {
+        /* grad F(q) = -D P_X(v + div q) */
+        orc_div(H, W, q, u);
+        for (size_t i = 0; i < n; ++i) {
+            u[i] += v[i];
+            if (nonneg && u[i] < 0.0) u[i] = 0.0;
+        }
+        orc_grad(H, W, u, g);
+        int th = orc_coin(seed, stream, k0 + it, p_in);
+        for (size_t i = 0; i < 2 * n; ++i) {
+            double w = q[i] + gamma * g[i];      /* q - gamma grad F(q) */
+            qhat[i] = w + gamma * h[i];
+            w2[i] = w + coef * h[i];
+        }
+        if (th) {
+            orc_proj_ball(n, w2, lam, q);
+            for (size_t i = 0; i < 2 * n; ++i) h[i] = h[i] + rate * (q[i] - qhat[i]);
+            ++nproj;
+        } else {
+            memcpy(q, qhat, 2 * n * sizeof(double));
+        }
+    }
+    orc_div(H, W, q, u);
+    for (size_t i = 0; i < n; ++i) {
+        double zi = v[i] + u[i];
+        z_out[i] = (nonneg && zi < 0.0) ? 0.0 : zi;
+    }
+    free(u); free(g); free(qhat); free(w2);
+    return nproj;
+}
+
+/* The inner coins of the prox call at outer iteration k come from the
+ * coin's generator on stream stream_id xor 2^62, indices k K_in + i, so a
+ * run resumed at k0 draws the same inner schedule. */
+#define ORC_INNER_STREAM 0x4000000000000000ULL
+
+/* Alg. "ProxSkip" with the TV prox by orc_tv_prox_skip (K_in = inner_iters
+ * inner ProxSkip steps, projection probability p_in, inner control variate
+ * h_in [2][H][W] kept across calls like the dual q).  n_proj_out (nullable)
+ * gets the number of inner projections.  Returns the number of prox calls. */
+int64_t orc_proxskip_inner(const orc_op* A, const double* b, double* x, double* h, double* q,
+                           double* h_in, double p_in, const orc_params* P,
+                           uint8_t* theta_trace, double* obj_trace, int64_t* n_proj_out) {
+    int H = A->H, W = A->W;
+    size_t n = (size_t)H * W, m = orc_op_out_size(A);
+    double gamma = P->step, p = P->p;
+    double lam = P->alpha * gamma / p;
+    double coef = gamma - gamma / p;
+    double rate = p / gamma;
+    double* res = dalloc(m);
+    double* g = dalloc(n);
+    double* w = dalloc(n);
+    double* xhat = dalloc(n);
+    double* v = dalloc(n);
+    double* z = dalloc(n);
+    int64_t nprox = 0, nproj = 0;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        int64_t k = P->k0 + kk;
+        data_grad(A, b, x, res, g);
+        for (size_t i = 0; i < n; ++i) {
+            w[i] = x[i] - gamma * g[i];
+            xhat[i] = w[i] + gamma * h[i];
+        }
+        int th = orc_coin(P->seed, P->stream_id, k, p);
+        if (th) {
+            for (size_t i = 0; i < n; ++i) v[i] = w[i] + coef * h[i];
+            nproj += orc_tv_prox_skip(H, W, v, lam, P->nonneg, P->inner_iters, p_in, P->seed,
+                                      P->stream_id ^ ORC_INNER_STREAM, k * P->inner_iters, q,
+                                      h_in, z);
+            for (size_t i = 0; i < n; ++i) {
+                h[i] = h[i] + rate * (z[i] - xhat[i]);
+                x[i] = z[i];
+            }
+            ++nprox;
+        } else {
+            memcpy(x, xhat, n * sizeof(double));
+        }
+        if (theta_trace) theta_trace[kk] = (uint8_t)th;
+        if (obj_trace) obj_trace[kk] = orc_objective(A, b, x, P->alpha);
+    }
+    if (n_proj_out) *n_proj_out = nproj;
+    free(res); free(g); free(w); free(xhat); free(v); free(z);
+    return nprox;
+}
+
+/* Alg. "PDHGSkip-2" with the TV prox by orc_tv_prox_skip (as above). */
+int64_t orc_pdhgskip_inner(const orc_op* A, const double* b, double* x, double* h, double* y,
+                           double* q, double* h_in, double p_in, const orc_params* P,
+                           uint8_t* theta_trace, double* obj_trace, int64_t* n_proj_out) {
+    int H = A->H, W = A->W;
+    size_t n = (size_t)H * W, m = orc_op_out_size(A);
+    double sigma = P->step, tau = P->dual_step, p = P->p;
+    double lam = P->alpha * sigma / p;
+    double coef = sigma - sigma / p;
+    double rate = p / sigma;
+    double* kty = dalloc(n);
+    double* w = dalloc(n);
+    double* xhat = dalloc(n);
+    double* v = dalloc(n);
+    double* z = dalloc(n);
+    double* xbar = dalloc(n);
+    double* kx = dalloc(m);
+    int64_t nprox = 0, nproj = 0;
+    for (int64_t kk = 0; kk < P->outer_iters; ++kk) {
+        int64_t k = P->k0 + kk;
+        orc_op_adjoint(A, y, kty);
+        for (size_t i = 0; i < n; ++i) {
+            w[i] = x[i] - sigma * kty[i];
+            xhat[i] = w[i] + sigma * h[i];
+        }
+        int th = orc_coin(P->seed, P->stream_id, k, p);
+        if (th) {
+            for (size_t i = 0; i < n; ++i) v[i] = w[i] + coef * h[i];
+            nproj += orc_tv_prox_skip(H, W, v, lam, P->nonneg, P->inner_iters, p_in, P->seed,
+                                      P->stream_id ^ ORC_INNER_STREAM, k * P->inner_iters, q,
+                                      h_in, z);
+            for (size_t i = 0; i < n; ++i) h[i] = h[i] + rate * (z[i] - xhat[i]);
+            ++nprox;
+        } else {
+            memcpy(z, xhat, n * sizeof(double));
+        }
+        for (size_t i = 0; i < n; ++i) {
+            xbar[i] = 2.0 * z[i] - x[i];
+            x[i] = z[i];
+        }
+        orc_op_apply(A, xbar, kx);
+        for (size_t i = 0; i < m; ++i) y[i] = (y[i] + tau * (kx[i] - b[i])) / (1.0 + tau);
+        if (theta_trace) theta_trace[kk] = (uint8_t)th;
+        if (obj_trace) obj_trace[kk] = orc_objective(A, b, x, P->alpha);
+    }
+    if (n_proj_out) *n_proj_out = nproj;
+    free(kty); free(w); free(xhat); free(v); free(z); free(xbar); free(kx);
+    return nprox;
+}

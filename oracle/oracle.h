@@ -144,6 +144,24 @@ int64_t orc_dual_rof_proxskip(int H, int W, const double* b, double alpha, doubl
 void orc_dual_rof_projgd(int H, int W, const double* b, double alpha, double eps, double gamma,
                          int64_t K, double* q);
 
+/* ---- skipping inside the inner solver ("Discussion and Future work"): the
+ * TV prox by ProxSkip on its dual (step 1/8, projection probability p_in,
+ * with u >= 0 the constrained dual, gradient -D P_X(v + div q)); q, h
+ * ([2][H][W]) in/out, z_out = P_X(v + div q).  Returns the projections. */
+int64_t orc_tv_prox_skip(int H, int W, const double* v, double lam, int nonneg, int iters,
+                         double p_in, uint64_t seed, uint64_t stream, int64_t k0, double* q,
+                         double* h, double* z_out);
+/* ProxSkip / PDHGSkip-2 with that prox: inner_iters inner steps per call,
+ * inner coins on stream stream_id xor 2^62 at indices k inner_iters + i
+ * (k the outer iteration), inner control variate h_in kept across calls.
+ * n_proj_out (nullable) gets the inner projections; returns the prox calls. */
+int64_t orc_proxskip_inner(const orc_op* A, const double* b, double* x, double* h, double* q,
+                           double* h_in, double p_in, const orc_params* P,
+                           uint8_t* theta_trace, double* obj_trace, int64_t* n_proj_out);
+int64_t orc_pdhgskip_inner(const orc_op* A, const double* b, double* x, double* h, double* y,
+                           double* q, double* h_in, double p_in, const orc_params* P,
+                           uint8_t* theta_trace, double* obj_trace, int64_t* n_proj_out);
+
 /* ---- learned TV prox (cnn.c): 2 -> 32 -> 32 -> 32 -> 2, 3x3, dual output ---- */
 #define ORC_CNN_LAYERS 4
 size_t orc_cnn_param_count(void);

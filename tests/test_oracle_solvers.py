@@ -121,13 +121,12 @@ def test_blur_proxskip_pgd_and_reference_solver_agree():
     assert np.max(np.abs(r_ps["x"] - ref["x"])) < 1e-4
 
 
-def test_ct_pdhgskip_and_reference_solver_agree():
+def test_ct_pdhgskip_and_reference_solver_agree(ct24_reference):
     """Small non-negative CT problem: PDHGSkip-2 (p = 0.3), PDHG and the
     diagonally preconditioned explicit PDHG reach one minimiser."""
-    A, _, b = small_ct()
-    alpha = 0.05
+    A, b, alpha, ref = ct24_reference
+    assert np.array_equal(b, small_ct()[2])
     L = A.norm(200)
-    ref = O.pdhg_explicit(A, b, alpha, 1, 100000)
     r_pd = O.pdhg(A, b, alpha, 1 / L, 1 / L, 4000, 30, nonneg=1)
     r_sk = O.pdhgskip(A, b, alpha, 1 / L, 1 / L, 0.3, 8000, 30, nonneg=1, seed=8)
     phis = [O.objective(A, b, x, alpha) for x in (ref["x"], r_pd["x"], r_sk["x"])]
