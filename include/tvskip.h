@@ -514,11 +514,25 @@ tvs_status tvs_cnn_prox(tvs_cnn* cnn, int H, int W, const float* v, double lam, 
  *    params->inner_iters FGP iterations run, warm-started from whichever of
  *    the two duals has the smaller relative gap.  A NaN gap falls back.
  *    float32 only (TVS_ERR_UNSUPPORTED else).
+ *  - inner_p > 0 (skipping inside the inner solver, the paper's
+ *    "Discussion and Future work"): every prox call solves the TV prox by
+ *    params->inner_iters steps of ProxSkip on its dual instead of FGP (the
+ *    dual of Sec. 2.1 with eps = 0; with nonneg the constrained dual, whose
+ *    gradient is -D max(v + div q, 0)), step 1/8 and projection probability
+ *    inner_p, warm-started from (state->q, inner_h).  inner_h: device, dtype,
+ *    [2][H][W], the inner control variate, kept across calls and runs like q
+ *    (zero it for a cold start).  The inner coin of step i of the call at
+ *    outer iteration k (k0 included) is the coin of tvs_proxskip on stream
+ *    stream_id xor 2^62 at index k inner_iters + i, so a resumed run draws
+ *    the same schedule.  float32 and float64; excludes cnn
+ *    (TVS_ERR_INVALID_ARG); inner_p outside (0, 1] or a NULL inner_h is
+ *    TVS_ERR_INVALID_ARG.  inner_p = 0: FGP as in the plain call.
  *  - v_record != NULL: the prox inputs v (the argument of the prox in
  *    Alg. "ProxSkip" / "PDHGSkip-2") of the first max_record prox calls are
  *    copied to v_record (device, dtype, max_record x H x W), the pairs that
  *    train the network.
- * Outputs: n_fallback = calls where FGP ran, n_recorded = inputs stored. */
+ * Outputs: n_fallback = calls where FGP ran, n_recorded = inputs stored,
+ * n_inner_proj = projections the skipping inner solver made. */
 typedef struct tvs_solve_ext {
     tvs_cnn* cnn;
     double gap_tol;
@@ -526,6 +540,9 @@ typedef struct tvs_solve_ext {
     int64_t max_record;
     int64_t n_fallback;   /* out */
     int64_t n_recorded;   /* out */
+    double inner_p;
+    void* inner_h;
+    int64_t n_inner_proj; /* out */
 } tvs_solve_ext;
 
 tvs_status tvs_proxskip_ex(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* state,

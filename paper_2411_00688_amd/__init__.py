@@ -246,17 +246,21 @@ def _solve(fn, op, b, x, h, q, y, alpha, step, dual_step, p, outer_iters, inner_
                obj=obj[:outer_iters] if want_obj else None,
                theta=th[:outer_iters] if want_theta else None)
     if ext is not None:
-        out.update(n_fallback=ext.n_fallback, n_recorded=ext.n_recorded)
+        out.update(n_fallback=ext.n_fallback, n_recorded=ext.n_recorded,
+                   n_inner_proj=ext.n_inner_proj)
     return out
 
 
-def _ext(cnn, gap_tol, v_record):
+def _ext(cnn, gap_tol, v_record, inner_p=0.0, inner_h=None, x=None):
     e = tvs_solve_ext()
     e.cnn = C.c_void_p(cnn) if cnn else None
     e.gap_tol = float(gap_tol)
     if v_record is not None:
         e.v_record = _ptr(v_record)
         e.max_record = int(v_record.shape[0])
+    e.inner_p = float(inner_p)
+    if inner_h is not None:
+        e.inner_h = _ptr(inner_h, 2 * x.numel(), _dtype_code(x))
     return e
 
 
@@ -351,20 +355,24 @@ def tvs_spdhgskip(op: int, b, x, h, q, y, n_subsets, alpha, sigma, tau, p, outer
 
 def tvs_proxskip_ex(op: int, b, x, h, q, alpha, step, p, outer_iters, inner_iters, nonneg=0,
                     seed=0, stream_id=0, k0=0, graph=False, want_obj=False, want_theta=False,
-                    cnn=None, gap_tol=1e-3, v_record=None):
-    """tvs_proxskip with the learned prox (cnn) and / or prox-input recording
-    (v_record: (max_record, H, W) tensor).  Adds n_fallback, n_recorded."""
+                    cnn=None, gap_tol=1e-3, v_record=None, inner_p=0.0, inner_h=None):
+    """tvs_proxskip with the learned prox (cnn), the skipping inner solver
+    (inner_p > 0 with its control variate inner_h, a (2, H, W) tensor kept
+    across runs) and / or prox-input recording (v_record: (max_record, H, W)
+    tensor).  Adds n_fallback, n_recorded, n_inner_proj."""
     return _solve(lib().tvs_proxskip_ex, op, b, x, h, q, None, alpha, step, 0.0, p, outer_iters,
                   inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta,
-                  ext=_ext(cnn, gap_tol, v_record))
+                  ext=_ext(cnn, gap_tol, v_record, inner_p, inner_h, x))
 
 
 def tvs_pdhgskip_ex(op: int, b, x, h, q, y, alpha, sigma, tau, p, outer_iters, inner_iters,
                     nonneg=0, seed=0, stream_id=0, k0=0, graph=False, want_obj=False,
-                    want_theta=False, cnn=None, gap_tol=1e-3, v_record=None):
+                    want_theta=False, cnn=None, gap_tol=1e-3, v_record=None, inner_p=0.0,
+                    inner_h=None):
+    """tvs_pdhgskip with the same extensions as tvs_proxskip_ex."""
     return _solve(lib().tvs_pdhgskip_ex, op, b, x, h, q, y, alpha, sigma, tau, p, outer_iters,
                   inner_iters, nonneg, seed, stream_id, k0, graph, want_obj, want_theta,
-                  ext=_ext(cnn, gap_tol, v_record))
+                  ext=_ext(cnn, gap_tol, v_record, inner_p, inner_h, x))
 
 
 # ------------------------------------------------------------- FGP tuning

@@ -53,7 +53,8 @@ class tvs_dual_rof_params(C.Structure):
 
 class tvs_solve_ext(C.Structure):
     _fields_ = [("cnn", C.c_void_p), ("gap_tol", C.c_double), ("v_record", C.c_void_p),
-                ("max_record", C.c_int64), ("n_fallback", C.c_int64), ("n_recorded", C.c_int64)]
+                ("max_record", C.c_int64), ("n_fallback", C.c_int64), ("n_recorded", C.c_int64),
+                ("inner_p", C.c_double), ("inner_h", C.c_void_p), ("n_inner_proj", C.c_int64)]
 
 
 class tvs_batch_params(C.Structure):

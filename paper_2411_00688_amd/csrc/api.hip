@@ -774,6 +774,11 @@ static void run_solver(tvs_op* op, bool pdhg, const T* b, const tvs_state* st,
                 qf = (T*)cnn::enqueue_solver_prox(ext.cnn, H, W, (const float*)v, lam, P->nonneg,
                                                   ext.gap_tol, P->inner_iters, (float*)q, cfg,
                                                   ext.gate + call);
+            } else if (ext.inner_p > 0) {
+                qf = run_tv_prox_skip<T>(ctx, H, W, v, lam, P->nonneg, P->inner_iters,
+                                         ext.inner_p,
+                                         ext.inner_theta + (size_t)call * P->inner_iters, q,
+                                         (T*)ext.inner_h);
             } else {
                 qf = run_fgp<T>(ctx, H, W, v, lam, P->inner_iters, P->nonneg, q, cfg);
             }
@@ -853,11 +858,37 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
         if (obj_trace && K > 0) obj_dev = (double*)scratch(ctx, S_OBJ, (size_t)K * sizeof(double));
         const bool use_graph = (P->flags & TVS_FLAG_GRAPH) && !obj_dev && K > 0;
         SolveExt ext;
+        std::vector<uint8_t> inner_theta;
+        int64_t n_inner_proj = 0;
         if (ext_io) {
             TVS_REQUIRE(ext_io->max_record >= 0 && (ext_io->v_record || ext_io->max_record == 0),
                         TVS_ERR_INVALID_ARG, "v_record required when max_record > 0");
             ext.v_record = ext_io->v_record;
             ext.max_record = ext_io->max_record;
+            if (ext_io->inner_p != 0.0) {
+                TVS_REQUIRE(ext_io->inner_p > 0 && ext_io->inner_p <= 1, TVS_ERR_INVALID_ARG,
+                            "inner_p must be in (0, 1]");
+                TVS_REQUIRE(ext_io->inner_h, TVS_ERR_INVALID_ARG,
+                            "inner_h required when inner_p > 0");
+                TVS_REQUIRE(!ext_io->cnn, TVS_ERR_INVALID_ARG,
+                            "the learned prox and the skipping inner solver exclude each other");
+                ext.inner_p = ext_io->inner_p;
+                ext.inner_h = ext_io->inner_h;
+                // inner coins: stream stream_id xor 2^62, index k inner_iters + i
+                const int Kin = P->inner_iters;
+                inner_theta.resize((size_t)nprox * Kin);
+                size_t c = 0;
+                for (int64_t kk = 0; kk < K; ++kk) {
+                    if (!theta[kk]) continue;
+                    const int64_t k = P->k0 + kk;
+                    for (int i = 0; i < Kin; ++i, ++c) {
+                        inner_theta[c] = (uint8_t)coin(P->seed, P->stream_id ^ INNER_STREAM,
+                                                       k * Kin + i, ext.inner_p);
+                        n_inner_proj += inner_theta[c];
+                    }
+                }
+                ext.inner_theta = inner_theta.data();
+            }
             if (ext_io->cnn) {
                 TVS_REQUIRE(dtype == TVS_F32, TVS_ERR_UNSUPPORTED,
                             "the learned prox runs on float32 only");
@@ -887,6 +918,9 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
                                    (uint64_t)(uintptr_t)ext.v_record, (uint64_t)ext.max_record,
                                    (uint64_t)(uintptr_t)ext.gate,
                                    ext.cnn ? (uint64_t)cnn::fast_forward(ext.cnn) : 0});
+            uint64_t pin_bits;
+            std::memcpy(&pin_bits, &ext.inner_p, sizeof(pin_bits));
+            key.insert(key.end(), {pin_bits, (uint64_t)(uintptr_t)ext.inner_h});
             graph_run_key(ctx, key, enqueue);
         } else {
             enqueue();
@@ -894,6 +928,7 @@ static tvs_status solve(tvs_op* op, tvs_dtype dtype, const void* b, tvs_state* s
         if (ext_io) {
             ext_io->n_recorded = nprox < ext.max_record ? nprox : ext.max_record;
             ext_io->n_fallback = 0;
+            ext_io->n_inner_proj = n_inner_proj;
             if (ext.cnn && nprox > 0) {
                 std::vector<int> g((size_t)nprox);
                 TVS_HIP(hipMemcpyAsync(g.data(), ext.gate, (size_t)nprox * sizeof(int),

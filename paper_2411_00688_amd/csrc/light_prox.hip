@@ -9,6 +9,10 @@
 // with probability p: q+ = P(w + (gamma - gamma / p) h), h += (p / gamma)(q+ -
 // qhat); else q+ = qhat.
 //
+// With the constraint z >= 0 (the TV prox of a non-negative image) the dual
+// is the constrained one of Beck and Teboulle 2009: grad F(q) = -D P_+(b +
+// div q), with eps = 0; the kernel clips z before its differences.
+//
 // The kernel fuses TS steps per launch on a tile with a TS-pixel halo (each
 // step widens the dependency cone by one pixel), the state (q, h) of every
 // pixel of the tile region in registers and q and z = div q + b exchanged
@@ -45,6 +49,7 @@ struct LpArgs {
     size_t plane;
     int nsteps;
     unsigned theta;  // bit s: prox at step s of this launch
+    int nonneg;      // z = max(b + div q, 0) (eps = 0 only)
     T alpha, gamma, mu, coef, rate;
 };
 
@@ -116,6 +121,7 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
             if (f & LF_DX) d += qx[p];
             if (f & LF_LEFT) d -= s_qx[idx - 1];
             zz[p] = bb[p] + d;
+            if (a.nonneg) zz[p] = zz[p] > T(0) ? zz[p] : T(0);
             if (idx < R) s_z[idx] = zz[p];
         }
         __syncthreads();
@@ -181,29 +187,18 @@ namespace {
 // kernel, shrinks faster than the extra launches' traffic grows).
 constexpr int LP_TS_SMALL = 8, LP_TS_BIG = 6;
 
+// Runs theta.size() steps from (q, h), each launch reading one pair of
+// buffers and writing the other; returns true when the result sits in (q2, h2).
 template <typename T>
-void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
-                  const tvs_dual_rof_params* P, const std::vector<uint8_t>& theta) {
-    const size_t n = (size_t)H * W;
-    T* q2 = (T*)scratch(ctx, S_Q1, 2 * n * sizeof(T));
-    T* h2 = (T*)scratch(ctx, S_Q2, 2 * n * sizeof(T));
-    const bool big = (long long)div_up(W, 32) * div_up(H, 32) >= 2LL * ctx->n_cu;
-    LpArgs<T> a;
-    a.b = b;
-    a.H = H;
-    a.W = W;
-    a.plane = n;
-    a.alpha = (T)P->alpha;
-    a.gamma = (T)P->step;
-    a.mu = (T)(P->alpha > 0 ? P->eps / P->alpha : 0.0);
-    a.coef = (T)(P->step - P->step / P->p);
-    a.rate = (T)(P->p / P->step);
+bool lp_steps(tvs_ctx* ctx, LpArgs<T> a, int64_t K, const uint8_t* theta, T* q, T* h, T* q2,
+              T* h2) {
+    const bool big = (long long)div_up(a.W, 32) * div_up(a.H, 32) >= 2LL * ctx->n_cu;
     const T* qi = q;
     const T* hi = h;
     bool in_caller = true;
     const int ts = big ? LP_TS_BIG : LP_TS_SMALL;
-    for (int64_t k = 0; k < P->outer_iters; k += ts) {
-        const int ns = (int)std::min<int64_t>(ts, P->outer_iters - k);
+    for (int64_t k = 0; k < K; k += ts) {
+        const int ns = (int)std::min<int64_t>(ts, K - k);
         unsigned mask = 0;
         for (int s = 0; s < ns; ++s) mask |= (unsigned)theta[(size_t)(k + s)] << s;
         a.q = qi;
@@ -221,9 +216,29 @@ void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
         hi = a.ho;
         in_caller = !in_caller;
     }
-    if (!in_caller) {
-        launch_copy<T>(ctx, 2 * n, qi, q);
-        launch_copy<T>(ctx, 2 * n, hi, h);
+    return !in_caller;
+}
+
+template <typename T>
+void run_dual_rof(tvs_ctx* ctx, int H, int W, const T* b, T* q, T* h,
+                  const tvs_dual_rof_params* P, const std::vector<uint8_t>& theta) {
+    const size_t n = (size_t)H * W;
+    T* q2 = (T*)scratch(ctx, S_Q1, 2 * n * sizeof(T));
+    T* h2 = (T*)scratch(ctx, S_Q2, 2 * n * sizeof(T));
+    LpArgs<T> a{};
+    a.b = b;
+    a.H = H;
+    a.W = W;
+    a.plane = n;
+    a.nonneg = 0;
+    a.alpha = (T)P->alpha;
+    a.gamma = (T)P->step;
+    a.mu = (T)(P->alpha > 0 ? P->eps / P->alpha : 0.0);
+    a.coef = (T)(P->step - P->step / P->p);
+    a.rate = (T)(P->p / P->step);
+    if (lp_steps<T>(ctx, a, P->outer_iters, theta.data(), q, h, q2, h2)) {
+        launch_copy<T>(ctx, 2 * n, q2, q);
+        launch_copy<T>(ctx, 2 * n, h2, h);
     }
 }
 
@@ -245,6 +260,38 @@ tvs_status guarded_lp(F&& f) {
 }
 
 }  // namespace
+
+namespace tvs {
+
+template <typename T>
+T* run_tv_prox_skip(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, int iters,
+                    double p_in, const uint8_t* theta, T* q, T* h) {
+    const size_t n = (size_t)H * W;
+    T* q2 = (T*)scratch(ctx, S_Q1, 2 * n * sizeof(T));
+    T* h2 = (T*)scratch(ctx, S_Q2, 2 * n * sizeof(T));
+    const double gamma = 0.125;
+    LpArgs<T> a{};
+    a.b = v;
+    a.H = H;
+    a.W = W;
+    a.plane = n;
+    a.nonneg = nonneg ? 1 : 0;
+    a.alpha = (T)lam;
+    a.gamma = (T)gamma;
+    a.mu = T(0);
+    a.coef = (T)(gamma - gamma / p_in);
+    a.rate = (T)(p_in / gamma);
+    if (!lp_steps<T>(ctx, a, iters, theta, q, h, q2, h2)) return q;
+    launch_copy<T>(ctx, 2 * n, h2, h);
+    return q2;
+}
+
+template float* run_tv_prox_skip<float>(tvs_ctx*, int, int, const float*, double, int, int,
+                                        double, const uint8_t*, float*, float*);
+template double* run_tv_prox_skip<double>(tvs_ctx*, int, int, const double*, double, int, int,
+                                          double, const uint8_t*, double*, double*);
+
+}  // namespace tvs
 
 extern "C" tvs_status tvs_dual_rof_proxskip(tvs_ctx* ctx, tvs_dtype dtype, int H, int W,
                                             const void* b, void* q, void* h,

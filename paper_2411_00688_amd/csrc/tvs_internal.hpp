@@ -340,6 +340,8 @@ void launch_combine(tvs_ctx* ctx, const double* x, double a, const double* y, do
 // host helpers
 uint64_t splitmix_mix(uint64_t z);
 int coin(uint64_t seed, uint64_t stream, int64_t k, double p);
+// the skipping inner solver draws its coins on stream stream_id xor 2^62
+constexpr uint64_t INNER_STREAM = 1ULL << 62;
 int subset_draw(uint64_t seed, uint64_t stream, int64_t k, int n);
 const double* beta_table_host(int n);
 
@@ -382,14 +384,25 @@ template <typename T>
 void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
                   T* q, T* z, double* rel_gap);
 
-// Optional parts of a solver run: the learned prox in place of FGP and the
-// recording of the prox inputs.
+// TV prox by ProxSkip on its dual (light_prox.hip): theta.size() = iters
+// steps with step 1/8 and projection probability p_in from the warm (q, h)
+// (the constrained dual when nonneg).  h ends in h; returns the buffer that
+// holds the final dual (q or a scratch buffer).  Enqueue only.
+template <typename T>
+T* run_tv_prox_skip(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, int iters,
+                    double p_in, const uint8_t* theta, T* q, T* h);
+
+// Optional parts of a solver run: the learned prox or the skipping inner
+// solver in place of FGP, and the recording of the prox inputs.
 struct SolveExt {
     tvs_cnn* cnn = nullptr;
     double gap_tol = 0.0;
     void* v_record = nullptr;   // device, max_record x H x W, the solver's dtype
     int64_t max_record = 0;
     int* gate = nullptr;        // device, one int per prox call (learned prox)
+    double inner_p = 0.0;       // > 0: the prox by run_tv_prox_skip
+    void* inner_h = nullptr;    // its control variate, device [2][H][W]
+    const uint8_t* inner_theta = nullptr;  // host, inner_iters coins per prox call
 };
 
 // learned prox (kernels_cnn.hip)

@@ -1,0 +1,223 @@
+"""GPU parity of the skipping inner solver (the paper's "Discussion and
+Future work": skipping inside the inner solver): ProxSkip / PDHGSkip-2 whose
+TV prox is ProxSkip on the dual (tvs_proxskip_ex / tvs_pdhgskip_ex with
+inner_p > 0).
+
+Bars as for the plain solvers: the outer coin schedule and the count of
+inner projections are exact; float64 runs agree with the oracle to 1e-10
+relative L2 (1e-9 for the control variates; FMA contraction on the GPU side
+only); float32 runs of the 512^2 CT workload to 1e-4 after 100 outer
+iterations; graph replays, resumed runs and both tile paths of the
+light-prox kernel change nothing.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2411_00688_amd as T
+import synth
+from gpu_util import (F32, F64, as_input, blur_problem, ct_problem, denoise_problem, dev, host,
+                      rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+def zeros(shape, dt):
+    return torch.zeros(shape, dtype=dt, device="cuda")
+
+
+def check(r, ref, pairs, tol=1e-10, tol_cv=1e-9):
+    assert np.array_equal(r["theta"], ref["theta"])
+    assert r["n_prox"] == ref["nprox"] and r["n_inner_proj"] == ref["nproj"]
+    for name, (gpu, want) in pairs.items():
+        t = tol_cv if name.startswith("h") else tol
+        assert rel_l2(host(gpu), want) < t, name
+
+
+@pytest.mark.parametrize("kind", ["ct", "blur", "identity_ragged"])
+def test_proxskip_inner_f64(ctx, kind):
+    if kind == "ct":
+        N = M = 32
+        ang, A, _, b = ct_problem(N, 24, 47, dtype=F64)
+        op = T.tvs_op_ct_joseph(ctx, N, N, ang, 47, 2 / N, 2 / N)
+        step, nonneg = 1 / A.norm(100) ** 2, 1
+    elif kind == "blur":
+        N = M = 40
+        k, A, _, b = blur_problem(N, dtype=F64)
+        op = T.tvs_op_blur_periodic(ctx, N, N, k)
+        step, nonneg = 1.0, 0
+    else:
+        N, M = 37, 45
+        b = as_input(synth.phantom_and_noise(N, M, 6, 8, (N, M))[0] - 0.2, F64)
+        A = O.identity(N, M)
+        op = T.tvs_op_identity(ctx, N, M)
+        step, nonneg = 1.0, 1
+    K, Kin, p, p_in = 40, 13, 0.3, 0.35      # Kin not a multiple of the fused depth
+    ref = O.proxskip_inner(A, b, 0.05, step, p, K, Kin, p_in, nonneg=nonneg, seed=4, stream=2)
+    try:
+        x, h = zeros((N, M), F64), zeros((N, M), F64)
+        q, hin = zeros((2, N, M), F64), zeros((2, N, M), F64)
+        r = T.tvs_proxskip_ex(op, dev(b, F64), x, h, q, 0.05, step, p, K, Kin, nonneg=nonneg,
+                              seed=4, stream_id=2, want_theta=True, inner_p=p_in, inner_h=hin)
+        check(r, ref, {"x": (x, ref["x"]), "q": (q, ref["q"]), "h": (h, ref["h"]),
+                       "h_in": (hin, ref["h_in"])})
+    finally:
+        T.tvs_op_destroy(op)
+
+
+@pytest.mark.parametrize("kind", ["ct", "identity"])
+def test_pdhgskip_inner_f64(ctx, kind):
+    N = 40
+    if kind == "ct":
+        ang, A, _, b = ct_problem(N, 30, 59, dtype=F64)
+        op = T.tvs_op_ct_joseph(ctx, N, N, ang, 59, 2 / N, 2 / N)
+        nonneg = 1
+    else:
+        _, b = denoise_problem(N)
+        A = O.identity(N, N)
+        op = T.tvs_op_identity(ctx, N, N)
+        nonneg = 0
+    L = A.norm(100)
+    K, Kin = 50, 20
+    ref = O.pdhgskip_inner(A, b, 0.05, 1 / L, 1 / L, 0.2, K, Kin, 0.25, nonneg=nonneg, seed=6,
+                           k0=11)
+    try:
+        x, h, y = zeros((N, N), F64), zeros((N, N), F64), zeros(A.out_shape, F64)
+        q, hin = zeros((2, N, N), F64), zeros((2, N, N), F64)
+        r = T.tvs_pdhgskip_ex(op, dev(b, F64), x, h, q, y, 0.05, 1 / L, 1 / L, 0.2, K, Kin,
+                              nonneg=nonneg, seed=6, k0=11, want_theta=True, inner_p=0.25,
+                              inner_h=hin)
+        check(r, ref, {"x": (x, ref["x"]), "y": (y, ref["y"]), "q": (q, ref["q"]),
+                       "h": (h, ref["h"]), "h_in": (hin, ref["h_in"])})
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_large_image_uses_the_wide_tiles(ctx):
+    """768 x 800 is large enough for the 32 x 32-tile path of the light-prox
+    kernel (6 fused steps per launch)."""
+    H, W = 768, 800
+    b = as_input(synth.phantom_and_noise(H, W, 12, 41, (H, W))[0] - 0.1, F64)
+    A = O.identity(H, W)
+    K, Kin = 3, 9
+    ref = O.proxskip_inner(A, b, 0.1, 1.0, 1.0, K, Kin, 0.3, nonneg=1, seed=9)
+    op = T.tvs_op_identity(ctx, H, W)
+    try:
+        x, h = zeros((H, W), F64), zeros((H, W), F64)
+        q, hin = zeros((2, H, W), F64), zeros((2, H, W), F64)
+        r = T.tvs_proxskip_ex(op, dev(b, F64), x, h, q, 0.1, 1.0, 1.0, K, Kin, nonneg=1, seed=9,
+                              want_theta=True, inner_p=0.3, inner_h=hin)
+        check(r, ref, {"x": (x, ref["x"]), "q": (q, ref["q"]), "h_in": (hin, ref["h_in"])})
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_pdhgskip_inner_ct512_f32_100_iters(ctx):
+    """The 512x512 CT workload (180 angles, 725 bins, non-negative, alpha
+    0.05, p 0.1) with 50 inner ProxSkip steps at p_in 0.3 per prox call,
+    first 100 outer iterations."""
+    w = synth.WORKLOADS["ct512"]
+    ang = synth.parallel_beam_angles(w.n_ang)
+    A = O.joseph(w.H, w.W, ang, w.n_det, w.pixel, w.det_spacing)
+    u, eta = synth.make_inputs(w)
+    Au = A.apply(u)
+    b = as_input(Au + w.noise * Au.max() * eta, F32)
+    L = A.norm(30)
+    K = 100
+    seed = synth.coin_seed(w.index)
+    ref = O.pdhgskip_inner(A, b, w.alpha, 1 / L, 1 / L, w.p, K, w.inner_iters, 0.3, nonneg=1,
+                           seed=seed, want_obj=True)
+    op = T.tvs_op_ct_joseph(ctx, w.H, w.W, ang, w.n_det, w.pixel, w.det_spacing)
+    try:
+        x, h = zeros((w.H, w.W), F32), zeros((w.H, w.W), F32)
+        q, hin = zeros((2, w.H, w.W), F32), zeros((2, w.H, w.W), F32)
+        y = zeros((w.n_ang, w.n_det), F32)
+        r = T.tvs_pdhgskip_ex(op, dev(b, F32), x, h, q, y, w.alpha, 1 / L, 1 / L, w.p, K,
+                              w.inner_iters, nonneg=1, seed=seed, want_theta=True,
+                              want_obj=True, inner_p=0.3, inner_h=hin)
+        assert np.array_equal(r["theta"], ref["theta"])
+        assert r["n_inner_proj"] == ref["nproj"]
+        assert rel_l2(host(x), ref["x"]) < 1e-4
+        assert rel_l2(host(y), ref["y"]) < 1e-4
+        assert np.max(np.abs(r["obj"] - ref["obj"]) / ref["obj"]) < 1e-5
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_graph_and_resume_are_bitwise(ctx):
+    N = 48
+    ang, A, _, b = ct_problem(N, 36, 69, dtype=F32)
+    L = A.norm(60)
+    op = T.tvs_op_ct_joseph(ctx, N, N, ang, 69, 2 / N, 2 / N)
+    bd = dev(b, F32)
+
+    def state():
+        return (zeros((N, N), F32), zeros((N, N), F32), zeros((2, N, N), F32),
+                zeros((36, 69), F32), zeros((2, N, N), F32))
+
+    def run(s, K, k0=0, graph=False):
+        x, h, q, y, hin = s
+        return T.tvs_pdhgskip_ex(op, bd, x, h, q, y, 0.05, 1 / L, 1 / L, 0.3, K, 11, nonneg=1,
+                                 seed=5, k0=k0, graph=graph, inner_p=0.4, inner_h=hin)
+
+    try:
+        ref = state()
+        r0 = run(ref, 30)
+        g = state()
+        for _ in range(3):          # capture, then replays from the same start
+            for t in g:
+                t.zero_()
+            torch.cuda.synchronize()
+            rg = run(g, 30, graph=True)
+            torch.cuda.synchronize()
+            for a, c in zip(ref, g):
+                assert torch.equal(a, c)
+            assert rg["n_inner_proj"] == r0["n_inner_proj"]
+        s = state()
+        ra = run(s, 13)
+        rb = run(s, 17, k0=13)
+        for a, c in zip(ref, s):
+            assert torch.equal(a, c)
+        assert ra["n_inner_proj"] + rb["n_inner_proj"] == r0["n_inner_proj"]
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_inner_p1_is_projgd(ctx):
+    """One outer step at p = 1 on A = I, gamma = 1 hands v = b to the prox;
+    with inner_p = 1 every inner step projects and the dual iterates are
+    ProjGD's (the coefficient of h in the projected point vanishes)."""
+    _, b = denoise_problem(24)
+    op = T.tvs_op_identity(ctx, 24, 24)
+    try:
+        x, h = zeros((24, 24), F64), zeros((24, 24), F64)
+        q, hin = zeros((2, 24, 24), F64), zeros((2, 24, 24), F64)
+        r = T.tvs_proxskip_ex(op, dev(b, F64), x, h, q, 0.1, 1.0, 1.0, 1, 7, seed=1,
+                              inner_p=1.0, inner_h=hin)
+        assert r["n_prox"] == 1 and r["n_inner_proj"] == 7
+        g = O.dual_rof_projgd(b, 0.1, 0.0, 1 / 8, 7)
+        assert rel_l2(host(q), g["q"]) < 1e-12
+        assert rel_l2(host(x), g["u"]) < 1e-12
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_invalid_inner_arguments(ctx):
+    _, b = denoise_problem(16)
+    op = T.tvs_op_identity(ctx, 16, 16)
+    cnn = T.tvs_cnn_create(ctx, 1)
+    try:
+        x, h, q, hin = (zeros((16, 16), F32), zeros((16, 16), F32), zeros((2, 16, 16), F32),
+                        zeros((2, 16, 16), F32))
+        bd = dev(b, F32)
+        for kw in (dict(inner_p=1.5, inner_h=hin), dict(inner_p=-0.1, inner_h=hin),
+                   dict(inner_p=0.5, inner_h=None), dict(inner_p=0.5, inner_h=hin, cnn=cnn)):
+            with pytest.raises(T.TvsError):
+                T.tvs_proxskip_ex(op, bd, x, h, q, 0.1, 1.0, 0.5, 5, 5, **kw)
+        with pytest.raises(ValueError):
+            T.tvs_proxskip_ex(op, bd, x, h, q, 0.1, 1.0, 0.5, 5, 5, inner_p=0.5,
+                              inner_h=zeros((16, 16), F32))
+    finally:
+        T.tvs_cnn_destroy(cnn)
+        T.tvs_op_destroy(op)
