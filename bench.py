@@ -280,18 +280,32 @@ def time_to_accuracy(solve, w, K, p_sweep=(0.1, 0.3, 0.5, 0.7), extra=None):
 def ct_comparisons(T, op, w, b, L, seed, K):
     """The paper's comparison methods on the CT workload: PDHGSkip-1 at p in
     {0.3, 0.7} (sigma = tau = 0.99 sqrt(p) / |A|, so that sigma tau (1 +
-    omega) |A|^2 < 1) and FISTA (step 1 / |A|^2), 50 inner iterations."""
+    omega) |A|^2 < 1) and FISTA (step 1 / |A|^2), 50 inner iterations; and
+    PDHGSkip-2 with skipping inside the inner solver (the TV prox by ProxSkip
+    on its dual, projection probability p_in = 0.3, K_in inner steps per
+    call) at (p, K_in) in {(0.1, 100), (0.3, 50), (0.3, 100)}."""
     import math
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
     N, na, nd = w.H, w.n_ang, w.n_det
     x = torch.zeros(N, N, device=dev)
+    h = torch.zeros_like(x)
     q = torch.zeros(2, N, N, device=dev)
+    hin = torch.zeros_like(q)
     y = torch.zeros(na, nd, device=dev)
 
     def entries(phis):
         out = {}
+        for pp, kin in ((0.1, 100), (0.3, 50), (0.3, 100)):
+            def run_in(iters, obj=False, pp=pp, kin=kin):
+                for t in (x, h, q, y, hin):
+                    t.zero_()
+                return T.tvs_pdhgskip_ex(op, b, x, h, q, y, w.alpha, 1.0 / L, 1.0 / L, pp, iters,
+                                         kin, nonneg=1, seed=seed, graph=not obj, want_obj=obj,
+                                         want_theta=obj, inner_p=0.3, inner_h=hin)
+            name = f"pdhgskip_p{pp}_inner_skip_k{kin}_p0.3"
+            out[name] = tta_entry(run_in, K, phis, name)
         for pp in (0.3, 0.7):
             s = 0.99 * math.sqrt(pp) / L
 
