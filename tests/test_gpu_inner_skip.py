@@ -94,6 +94,27 @@ def test_pdhgskip_inner_f64(ctx, kind):
         T.tvs_op_destroy(op)
 
 
+@pytest.mark.parametrize("H,W,Kin", [(1, 70, 9), (61, 1, 9), (20, 23, 1)])
+def test_thin_images_and_single_inner_steps(ctx, H, W, Kin):
+    """1 x N and N x 1 images (the dual has one plane of differences) and one
+    inner step per prox call, from a warm dual."""
+    b = as_input(np.random.default_rng(H + W).random((H, W)) - 0.3, F64)
+    A = O.identity(H, W)
+    K = 25
+    ref = O.proxskip_inner(A, b, 0.05, 1.0, 0.4, K, Kin, 0.3, nonneg=1, seed=3, x=b,
+                           q=0.01 * np.ones((2, H, W)))
+    op = T.tvs_op_identity(ctx, H, W)
+    try:
+        x, h = dev(b, F64), zeros((H, W), F64)
+        q, hin = dev(0.01 * np.ones((2, H, W)), F64), zeros((2, H, W), F64)
+        r = T.tvs_proxskip_ex(op, dev(b, F64), x, h, q, 0.05, 1.0, 0.4, K, Kin, nonneg=1, seed=3,
+                              want_theta=True, inner_p=0.3, inner_h=hin)
+        check(r, ref, {"x": (x, ref["x"]), "q": (q, ref["q"]), "h": (h, ref["h"]),
+                       "h_in": (hin, ref["h_in"])})
+    finally:
+        T.tvs_op_destroy(op)
+
+
 def test_large_image_uses_the_wide_tiles(ctx):
     """768 x 800 is large enough for the 32 x 32-tile path of the light-prox
     kernel (6 fused steps per launch)."""
