@@ -187,8 +187,9 @@ namespace {
 // kernel, shrinks faster than the extra launches' traffic grows).
 constexpr int LP_TS_SMALL = 8, LP_TS_BIG = 6;
 
-// Runs theta.size() steps from (q, h), each launch reading one pair of
-// buffers and writing the other; returns true when the result sits in (q2, h2).
+// Runs K steps (coins theta[0 .. K)) from (q, h), each launch reading one
+// pair of buffers and writing the other; returns true when the result sits
+// in (q2, h2).
 template <typename T>
 bool lp_steps(tvs_ctx* ctx, LpArgs<T> a, int64_t K, const uint8_t* theta, T* q, T* h, T* q2,
               T* h2) {

@@ -384,10 +384,10 @@ template <typename T>
 void tv_prox_impl(tvs_ctx* ctx, int H, int W, const T* v, double lambda, int iters, int nonneg,
                   T* q, T* z, double* rel_gap);
 
-// TV prox by ProxSkip on its dual (light_prox.hip): theta.size() = iters
-// steps with step 1/8 and projection probability p_in from the warm (q, h)
-// (the constrained dual when nonneg).  h ends in h; returns the buffer that
-// holds the final dual (q or a scratch buffer).  Enqueue only.
+// TV prox by ProxSkip on its dual (light_prox.hip): iters steps (coins
+// theta[0 .. iters)) with step 1/8 and projection probability p_in from the
+// warm (q, h) (the constrained dual when nonneg).  h ends in h; returns the
+// buffer that holds the final dual (q or a scratch buffer).  Enqueue only.
 template <typename T>
 T* run_tv_prox_skip(tvs_ctx* ctx, int H, int W, const T* v, double lam, int nonneg, int iters,
                     double p_in, const uint8_t* theta, T* q, T* h);
