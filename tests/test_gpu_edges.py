@@ -94,3 +94,33 @@ def test_size_limits_rejected(ctx):
     with pytest.raises((T.TvsError, ValueError)):
         T.tvs_tv_prox(ctx, v, -1.0, 3, 0, torch.zeros(2, 1, 1, device="cuda"),
                       torch.zeros(1, 1, device="cuda"))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_zero_outer_iterations_change_nothing(ctx, graph):
+    """outer_iters = 0 is a valid empty run for every solver entry point: the
+    state comes back bit for bit and no prox call is counted."""
+    N, na, nd = 24, 12, 35
+    ang = synth.parallel_beam_angles(na)
+    op = T.tvs_op_ct_joseph(ctx, N, N, ang, nd, 2 / N, 2 / N)
+    try:
+        r = np.random.default_rng(5)
+        b = dev(r.random((na, nd)), F32)
+        st = [dev(r.random(s), F32) for s in ((N, N), (N, N), (2, N, N), (na, nd), (2, N, N))]
+        before = [t.clone() for t in st]
+        x, h, q, y, hin = st
+        outs = [
+            T.tvs_proxskip(op, b, x, h, q, 0.05, 0.1, 0.3, 0, 5, graph=graph),
+            T.tvs_pdhgskip(op, b, x, h, q, y, 0.05, 0.3, 0.3, 0.3, 0, 5, graph=graph),
+            T.tvs_pdhgskip_ex(op, b, x, h, q, y, 0.05, 0.3, 0.3, 0.3, 0, 5, graph=graph,
+                              inner_p=0.3, inner_h=hin),
+            T.tvs_spdhgskip(op, b, x, h, q, y, 3, 0.05, 0.1, 0.3, 0.3, 0, 5, graph=graph),
+        ]
+        torch.cuda.synchronize()
+        for o in outs:
+            assert o["n_prox"] == 0 and o["iters"] == 0
+        assert outs[2]["n_inner_proj"] == 0
+        for a, c in zip(before, st):
+            assert torch.equal(a, c)
+    finally:
+        T.tvs_op_destroy(op)
