@@ -38,6 +38,13 @@ Parity status of each function (what pins it lives in tests/test_oracle_*.py):
                                      Dual-ROF and Dual-Huber-ROF; the primal
                                      iterate reaches the TV prox, 1-D taut
                                      string; duality gap -> 0)
+  tv_prox_skip .................... pinned (unconstrained: the separately
+                                     written Dual-ROF ProxSkip bitwise, ProjGD
+                                     at p_in = 1; 1-D taut string, clipped
+                                     with u >= 0; constrained gap -> 0)
+  proxskip_inner / pdhgskip_inner . pinned (one step on A = I is the TV prox;
+                                     reference minimisers of denoising and CT;
+                                     bitwise resume; inner coin stream)
   cnn_forward ..................... pinned (layers against scipy correlate2d,
                                      head closed form with zero weights)
   cnn_loss_grad ................... pinned (central finite differences)
