@@ -99,3 +99,48 @@ def test_learned_prox_parameter_count_and_null_checks():
     assert L.tvs_cnn_create(None, 0, C.byref(out)) == 1
     assert L.tvs_cnn_forward(None, 1, 4, 4, None, None, 0, None, None) == 1
     assert L.tvs_cnn_prox(None, 4, 4, None, 0.1, 0, 1e-3, 10, None, None, None, None) == 1
+
+
+STRUCTS = ("tvs_params", "tvs_state", "tvs_report", "tvs_slice", "tvs_dual_rof_params",
+           "tvs_solve_ext", "tvs_batch_params")
+
+
+def test_header_compiles_as_c_and_matches_the_binding_layout(tmp_path):
+    """A C99 program built against include/tvskip.h and linked with the
+    library: every struct's size and field offsets equal the ctypes
+    declarations of the binding, and the coin called from C equals the
+    oracle's."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tvskip.h"', 'int main(void) {']
+    for s in STRUCTS:
+        lines.append(f'    printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in getattr(_lib, s)._fields_:
+            lines.append(f'    printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append('    printf("coin %d\\n", tvs_coin(12345u, 7u, 99, 0.3));')
+    lines.append('    return 0;\n}')
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = tmp_path / "abi"
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-o", str(exe), "-L", libdir, "-ltvskip",
+                        f"-Wl,-rpath,{libdir}"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        parts = ln.split()
+        if len(parts) == 3:
+            got[(parts[0], parts[1])] = int(parts[2])
+        elif len(parts) == 2:
+            got[(parts[0], None)] = int(parts[1])
+    for s in STRUCTS:
+        cls = getattr(_lib, s)
+        assert got[(s, "size")] == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)
+    assert got[("coin", None)] == O.coin(12345, 7, 99, 0.3)
