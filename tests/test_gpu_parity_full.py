@@ -16,7 +16,8 @@ skip stretch, and the next prox call removes it again (measured 9.5e-4
 before a prox, 1e-7 after).  So every iteration is held to 2e-3 and the
 iterations that end with a prox call to 1e-5.  Also the deblurring workload's other
 two skip probabilities (p = 0.05, 0.3) for 100 iterations against the oracle
-run here."""
+run here, and the CT workload with the skipping inner solver for 1000
+iterations against its stored oracle run."""
 import os
 
 import numpy as np
@@ -44,11 +45,11 @@ def zeros(shape):
     return torch.zeros(shape, dtype=F32, device="cuda")
 
 
-def check_objective(name, obj, ref, theta, rel1000, rel_end):
+def check_objective(name, obj, ref, theta, rel1000, rel_end, mid=1000):
     dev_all = np.abs(obj - ref) / ref
     prox = theta.astype(bool)
     dev_prox = dev_all[prox]
-    print(f"{name}: rel L2 x at 1000 {rel1000:.2e}, at the end {rel_end:.2e}; objective "
+    print(f"{name}: rel L2 x at {mid} {rel1000:.2e}, at the end {rel_end:.2e}; objective "
           f"{dev_all.max():.2e} over all iterations, {dev_prox.max():.2e} after prox calls")
     assert rel1000 < 1e-3
     assert rel_end < 1e-3
@@ -98,6 +99,52 @@ def deblur_inputs():
     u, eta = synth.make_inputs(w)
     b = as_input(A.apply(u) + w.noise * eta, F32)
     return w, k, A, b
+
+
+def test_pdhgskip_inner_ct512_full_run(ctx):
+    """The CT workload with the skipping inner solver (PDHGSkip-2 at p = 0.3,
+    50 inner ProxSkip steps per prox call at projection probability 0.3, the
+    benchmark's inner-skip configuration), 1000 outer iterations in two
+    graph runs of 500 against the oracle's stored run."""
+    g = golden("parity_ct512_pdhgskip_inner.npz")
+    w = synth.WORKLOADS["ct512"]
+    ang = synth.parallel_beam_angles(w.n_ang)
+    A = O.joseph(w.H, w.W, ang, w.n_det, w.pixel, w.det_spacing)
+    u, eta = synth.make_inputs(w)
+    Au = A.apply(u)
+    b = as_input(Au + w.noise * Au.max() * eta, F32)
+    sigma, tau, seed = float(g["sigma"]), float(g["tau"]), int(g["seed"])
+    p, p_in, K = float(g["p"]), float(g["p_in"]), len(g["obj"])
+    op = T.tvs_op_ct_joseph(ctx, w.H, w.W, ang, w.n_det, w.pixel, w.det_spacing)
+
+    def state():
+        return [zeros((w.H, w.W)), zeros((w.H, w.W)), zeros((2, w.H, w.W)),
+                zeros((w.n_ang, w.n_det)), zeros((2, w.H, w.W))]
+
+    try:
+        bt = dev(b, F32)
+        x, h, q, y, hin = st = state()
+        n_proj = 0
+        for k0, n in ((0, K // 2), (K // 2, K - K // 2)):
+            r = T.tvs_pdhgskip_ex(op, bt, x, h, q, y, w.alpha, sigma, tau, p, n, w.inner_iters,
+                                  nonneg=1, seed=seed, k0=k0, graph=True, inner_p=p_in,
+                                  inner_h=hin)
+            n_proj += r["n_inner_proj"]
+            if k0 == 0:
+                x_half = host(x)
+        x_end = host(x)
+        x2, h2, q2, y2, hin2 = state()
+        r = T.tvs_pdhgskip_ex(op, bt, x2, h2, q2, y2, w.alpha, sigma, tau, p, K, w.inner_iters,
+                              nonneg=1, seed=seed, want_obj=True, want_theta=True, inner_p=p_in,
+                              inner_h=hin2)
+        assert np.array_equal(host(x2), x_end)
+        assert np.array_equal(r["theta"], g["theta"])
+        assert n_proj == r["n_inner_proj"] == int(g["n_inner_proj"])
+        check_objective("ct512 inner skip", r["obj"], g["obj"], g["theta"],
+                        rel_l2(x_half, g[f"x_{K // 2}"]), rel_l2(x_end, g[f"x_{K}"]),
+                        mid=K // 2)
+    finally:
+        T.tvs_op_destroy(op)
 
 
 def test_proxskip_deblur512_full_run(ctx):
