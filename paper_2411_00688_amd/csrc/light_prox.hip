@@ -19,6 +19,7 @@
 // through LDS.  The coin of the fused steps comes in as a bit mask (bit s =
 // theta of the launch's step s), known on the host before anything runs.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "tvs_internal.hpp"
@@ -61,15 +62,24 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
     constexpr int NT = 256;
     constexpr int RW = BW + 2 * TS, RH = BH + 2 * TS, R = RW * RH;
     constexpr int PPT = (R + NT - 1) / NT;
-    __shared__ T s_qy[R];
-    __shared__ T s_qx[R];
-    __shared__ T s_z[R];
+    // one guard row before and after each array (read by the flag-free steps)
+    __shared__ T s_qy_g[R + 2 * RW];
+    __shared__ T s_qx_g[R + 2 * RW];
+    __shared__ T s_z_g[R + 2 * RW];
+    T* const s_qy = s_qy_g + RW;
+    T* const s_qx = s_qx_g + RW;
+    T* const s_z = s_z_g + RW;
 
     const int H = a.H, W = a.W;
     const int gx = div_up(W, BW);
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int i0 = (t / gx) * BH - TS, j0 = (t % gx) * BW - TS;
     const int tid = (int)threadIdx.x;
+    // A region that holds neither the image's last row nor its last column
+    // steps without flags: away from its edge every pixel has all four
+    // neighbours, and its edge pixels (wrong either way) reach only the TS-wide
+    // halo within TS steps.
+    const bool interior = i0 >= 0 && j0 >= 0 && i0 + RH < H && j0 + RW < W;
 
     T qy[PPT], qx[PPT], hy[PPT], hx[PPT], bb[PPT], zz[PPT];
     int fl[PPT];
@@ -99,6 +109,8 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
         bb[p] = in ? a.b[g] : T(0);
     }
 
+    auto steps = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
     for (int s = 0; s < a.nsteps; ++s) {
         const bool prox = (a.theta >> s) & 1u;
 #pragma unroll
@@ -110,16 +122,27 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
             }
         }
         __syncthreads();
-        // z = b + div q  (u = b + div q, Sec. 2.1)
+        // z = b + div q  (u = b + div q, Sec. 2.1), the terms in the same
+        // order either way
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const int idx = tid + p * NT;
-            const int f = fl[p];
-            T d = T(0);
-            if (f & LF_DY) d += qy[p];
-            if (f & LF_UP) d -= s_qy[idx - RW];
-            if (f & LF_DX) d += qx[p];
-            if (f & LF_LEFT) d -= s_qx[idx - 1];
+            T d;
+            if (FAST) {
+                // slots past the region (last p only) read in-bounds guard
+                // values and store nothing
+                d = qy[p];
+                d -= s_qy[idx < R ? idx - RW : 0];
+                d += qx[p];
+                d -= s_qx[idx < R ? idx - 1 : 0];
+            } else {
+                const int f = fl[p];
+                d = T(0);
+                if (f & LF_DY) d += qy[p];
+                if (f & LF_UP) d -= s_qy[idx - RW];
+                if (f & LF_DX) d += qx[p];
+                if (f & LF_LEFT) d -= s_qx[idx - 1];
+            }
             zz[p] = bb[p] + d;
             if (a.nonneg) zz[p] = zz[p] > T(0) ? zz[p] : T(0);
             if (idx < R) s_z[idx] = zz[p];
@@ -130,8 +153,14 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
         for (int p = 0; p < PPT; ++p) {
             const int idx = tid + p * NT;
             const int f = fl[p];
-            const T dy = (f & LF_DOWN) ? s_z[idx + RW] - zz[p] : T(0);
-            const T dx = (f & LF_RIGHT) ? s_z[idx + 1] - zz[p] : T(0);
+            T dy, dx;
+            if (FAST) {
+                dy = s_z[idx < R ? idx + RW : 0] - zz[p];
+                dx = s_z[idx < R ? idx + 1 : 0] - zz[p];
+            } else {
+                dy = (f & LF_DOWN) ? s_z[idx + RW] - zz[p] : T(0);
+                dx = (f & LF_RIGHT) ? s_z[idx + 1] - zz[p] : T(0);
+            }
             const T gyv = -dy + a.mu * qy[p];
             const T gxv = -dx + a.mu * qx[p];
             const T wy = qy[p] - a.gamma * gyv, wx = qx[p] - a.gamma * gxv;
@@ -148,12 +177,17 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
                 qy[p] = hy_;
                 qx[p] = hx_;
             }
-            if (!(f & LF_IN)) qy[p] = qx[p] = hy[p] = hx[p] = T(0);
+            if (!FAST && !(f & LF_IN)) qy[p] = qx[p] = hy[p] = hx[p] = T(0);
         }
         // No barrier here: the next step writes s_qy / s_qx (last read before
         // this step's second barrier) and writes s_z only after its own first
         // barrier.
     }
+    };
+    if (interior)
+        steps(std::true_type{});
+    else
+        steps(std::false_type{});
 
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
