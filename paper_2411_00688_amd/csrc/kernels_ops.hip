@@ -3,11 +3,18 @@
 //
 //  - identity: pointwise, 32 x 32 tiles.
 //  - periodic blur: LDS tile with a periodic halo (radius <= 8).
-//  - Joseph parallel-beam projector (ray-driven, one wavefront per 64 adjacent
-//    bins of one angle, the row range split over 4 wavefronts and summed in a
-//    fixed order), and its exact transpose as a pixel-driven gather (no
-//    atomics): each pixel finds, per angle, the few rays whose interpolation
-//    touches it and recomputes their weights with the projector's arithmetic.
+//  - Joseph parallel-beam projector, ray-driven: the general kernel takes one
+//    wavefront per 64 adjacent bins of one angle with the row range split over
+//    8 wavefronts and summed in a fixed order; in float32, when the detector
+//    spacing is 1 to 2 pixels along the interpolation axis, the paired kernel
+//    lets each lane carry two adjacent rays from one 16-byte gather.
+//  - its exact transpose (no atomics, fixed summation order): in general a
+//    pixel-driven gather (each pixel finds, per angle, the few rays whose
+//    interpolation touches it and recomputes their weights with the
+//    projector's arithmetic); in float32, when every angle's rays fit the
+//    staged windows, a ray-driven scatter over 52 x 52 tiles and groups of
+//    angles (lane permutes move each ray's two weights to its pixels' lanes)
+//    whose per-group partial images a second kernel adds in order.
 //
 // Data-fidelity epilogue (PrimalStep), with s = grad f(x) (ProxSkip) or
 // s = A^T y (PDHGSkip-2) at a pixel:
