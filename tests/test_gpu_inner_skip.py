@@ -6,8 +6,8 @@ inner_p > 0).
 Bars as for the plain solvers: the outer coin schedule and the count of
 inner projections are exact; float64 runs agree with the oracle to 1e-10
 relative L2 (1e-9 for the control variates; FMA contraction on the GPU side
-only); float32 runs of the 512^2 CT workload to 1e-4 after 100 outer
-iterations; graph replays, resumed runs and both tile paths of the
+only); float32 runs of the 512^2 CT and deblurring workloads to 1e-4 after
+100 outer iterations; graph replays, resumed runs and both tile paths of the
 light-prox kernel change nothing.
 """
 import numpy as np
@@ -161,6 +161,33 @@ def test_pdhgskip_inner_ct512_f32_100_iters(ctx):
         assert r["n_inner_proj"] == ref["nproj"]
         assert rel_l2(host(x), ref["x"]) < 1e-4
         assert rel_l2(host(y), ref["y"]) < 1e-4
+        assert np.max(np.abs(r["obj"] - ref["obj"]) / ref["obj"]) < 1e-5
+    finally:
+        T.tvs_op_destroy(op)
+
+
+def test_proxskip_inner_deblur512_f32_100_iters(ctx):
+    """The 512x512 deblurring workload (periodic 9x9 Gaussian blur, alpha
+    0.02) with ProxSkip at p 0.3 and 50 inner ProxSkip steps at p_in 0.3 per
+    prox call (the unconstrained dual), first 100 outer iterations."""
+    w = synth.WORKLOADS["deblur512"]
+    k = synth.gaussian_blur_kernel(w.blur_size, w.blur_sigma)
+    A = O.blur(w.H, w.W, k)
+    u, eta = synth.make_inputs(w)
+    b = as_input(A.apply(u) + w.noise * eta, F32)
+    K, seed = 100, synth.coin_seed(w.index)
+    ref = O.proxskip_inner(A, b, w.alpha, 1.0, 0.3, K, w.inner_iters, 0.3, seed=seed,
+                           want_obj=True)
+    op = T.tvs_op_blur_periodic(ctx, w.H, w.W, k)
+    try:
+        x, h = zeros((w.H, w.W), F32), zeros((w.H, w.W), F32)
+        q, hin = zeros((2, w.H, w.W), F32), zeros((2, w.H, w.W), F32)
+        r = T.tvs_proxskip_ex(op, dev(b, F32), x, h, q, w.alpha, 1.0, 0.3, K, w.inner_iters,
+                              seed=seed, want_theta=True, want_obj=True, inner_p=0.3,
+                              inner_h=hin)
+        assert np.array_equal(r["theta"], ref["theta"])
+        assert r["n_inner_proj"] == ref["nproj"]
+        assert rel_l2(host(x), ref["x"]) < 1e-4
         assert np.max(np.abs(r["obj"] - ref["obj"]) / ref["obj"]) < 1e-5
     finally:
         T.tvs_op_destroy(op)
