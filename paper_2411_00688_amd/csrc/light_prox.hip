@@ -57,9 +57,8 @@ struct LpArgs {
 enum : int { LF_IN = 1, LF_DY = 2, LF_UP = 4, LF_DX = 8, LF_LEFT = 16, LF_DOWN = 32,
              LF_RIGHT = 64, LF_OUT = 128 };
 
-template <typename T, int BW, int BH, int TS>
-__global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
-    constexpr int NT = 256;
+template <typename T, int BW, int BH, int TS, int NT>
+__global__ __launch_bounds__(NT) void dual_rof_tb_kernel(LpArgs<T> a) {
     constexpr int RW = BW + 2 * TS, RH = BH + 2 * TS, R = RW * RH;
     constexpr int PPT = (R + NT - 1) / NT;
     // one guard row before and after each array (read by the flag-free steps)
@@ -203,10 +202,10 @@ __global__ __launch_bounds__(256) void dual_rof_tb_kernel(LpArgs<T> a) {
     }
 }
 
-template <typename T, int BW, int BH, int TS>
+template <typename T, int BW, int BH, int TS, int NT>
 static void launch_lp(const LpArgs<T>& a, hipStream_t st) {
     const int tiles = div_up(a.W, BW) * div_up(a.H, BH);
-    hipLaunchKernelGGL((dual_rof_tb_kernel<T, BW, BH, TS>), dim3(tiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((dual_rof_tb_kernel<T, BW, BH, TS, NT>), dim3(tiles), dim3(NT), 0, st, a);
 }
 
 }  // namespace tvs
@@ -215,10 +214,13 @@ using namespace tvs;
 
 namespace {
 
-// Small images use 16 x 16 tiles with 8 steps per launch so that the launch
-// still fills the GPU; large ones 32 x 32 tiles with 6 steps (40 x 40
-// regions instead of 48 x 48: the halo recomputation, which bounds the
-// kernel, shrinks faster than the extra launches' traffic grows).
+// Large images (at least two 32 x 32 tiles per CU) use 32 x 32 tiles with 6
+// steps per launch (40 x 40 regions instead of 48 x 48: the halo
+// recomputation, which bounds the kernel, shrinks faster than the extra
+// launches' traffic grows); images with one such tile per CU 32 x 32 tiles
+// with 8 steps; both with 1024-thread workgroups, so that a CU runs 16 waves
+// of one tile.  Smaller images use 16 x 16 tiles with 8 steps and 256
+// threads so that the launch still fills the GPU.
 constexpr int LP_TS_SMALL = 8, LP_TS_BIG = 6;
 
 // Runs K steps (coins theta[0 .. K)) from (q, h), each launch reading one
@@ -227,7 +229,9 @@ constexpr int LP_TS_SMALL = 8, LP_TS_BIG = 6;
 template <typename T>
 bool lp_steps(tvs_ctx* ctx, LpArgs<T> a, int64_t K, const uint8_t* theta, T* q, T* h, T* q2,
               T* h2) {
-    const bool big = (long long)div_up(a.W, 32) * div_up(a.H, 32) >= 2LL * ctx->n_cu;
+    const long long t32 = (long long)div_up(a.W, 32) * div_up(a.H, 32);
+    const bool big = t32 >= 2LL * ctx->n_cu;
+    const bool mid = !big && t32 >= ctx->n_cu;
     const T* qi = q;
     const T* hi = h;
     bool in_caller = true;
@@ -243,9 +247,11 @@ bool lp_steps(tvs_ctx* ctx, LpArgs<T> a, int64_t K, const uint8_t* theta, T* q, 
         a.nsteps = ns;
         a.theta = mask;
         if (big)
-            launch_lp<T, 32, 32, LP_TS_BIG>(a, ctx->stream);
+            launch_lp<T, 32, 32, LP_TS_BIG, 1024>(a, ctx->stream);
+        else if (mid)
+            launch_lp<T, 32, 32, LP_TS_SMALL, 1024>(a, ctx->stream);
         else
-            launch_lp<T, 16, 16, LP_TS_SMALL>(a, ctx->stream);
+            launch_lp<T, 16, 16, LP_TS_SMALL, 256>(a, ctx->stream);
         TVS_LAUNCH_CHECK();
         qi = a.qo;
         hi = a.ho;
