@@ -590,6 +590,8 @@ static const FgpVariant kFgpVariants[] = {
     {16, 16, 8}, {32, 16, 4}, {32, 16, 8}, {16, 16, 2}, {16, 16, 5},
     // row-walking strips (HBM-bound sizes): one iteration per launch, or four
     {256, 8, 1, 1}, {248, 32, 4, 1}, {248, 64, 4, 1},
+    // 1024-thread tiles at other depths (5 and 10 divide 50)
+    {32, 32, 5}, {32, 32, 6}, {64, 16, 8},
 };
 
 template <typename T>
@@ -605,7 +607,7 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
     TVS_FGPV(32, 32, 1) TVS_FGPV(32, 32, 2) TVS_FGPV(32, 32, 4) TVS_FGPV(32, 32, 8)
     TVS_FGPV(64, 16, 1) TVS_FGPV(64, 16, 4) TVS_FGPV(64, 32, 4) TVS_FGPV(16, 16, 4)
     TVS_FGPV(16, 16, 8) TVS_FGPV(32, 16, 4) TVS_FGPV(32, 16, 8) TVS_FGPV(16, 16, 2)
-    TVS_FGPV(16, 16, 5)
+    TVS_FGPV(16, 16, 5) TVS_FGPV(32, 32, 5) TVS_FGPV(32, 32, 6) TVS_FGPV(64, 16, 8)
     if (sizeof(T) == 4) { TVS_FGPV(64, 32, 8) }
 #undef TVS_FGPV
     const dim3 sgrid(div_up(a.W, 256) * div_up(a.H, V.bh));
@@ -726,7 +728,7 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
     TVS_FGPB(32, 32, 1) TVS_FGPB(32, 32, 2) TVS_FGPB(32, 32, 4) TVS_FGPB(32, 32, 8)
     TVS_FGPB(64, 16, 1) TVS_FGPB(64, 16, 4) TVS_FGPB(64, 32, 4) TVS_FGPB(16, 16, 4)
     TVS_FGPB(16, 16, 8) TVS_FGPB(32, 16, 4) TVS_FGPB(32, 16, 8) TVS_FGPB(16, 16, 2)
-    TVS_FGPB(16, 16, 5)
+    TVS_FGPB(16, 16, 5) TVS_FGPB(32, 32, 5) TVS_FGPB(32, 32, 6) TVS_FGPB(64, 16, 8)
     if (sizeof(T) == 4) { TVS_FGPB(64, 32, 8) }
 #undef TVS_FGPB
 #define TVS_FGPS(RC_)                                                                            \
