@@ -799,20 +799,24 @@ T* run_fgp_batched(tvs_ctx* ctx, const BSlice<T>* sl, const BatchLists& L, const
 // z = P_X(v + div q) and the bookkeeping that follows a prox evaluation.
 // 32 x 32 tiles, 256 threads (4 pixels each); the transposed copy of xbar
 // goes through LDS so that both stores are coalesced.
+// finalize: one 32 x 32 tile per workgroup, one pixel per thread
+constexpr int FIN_NT = 1024, FIN_PPT = 1024 / FIN_NT;
+
 template <typename T>
-__global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int W) {
+__global__ __launch_bounds__(FIN_NT) void finalize_kernel(Finalize<T> f, int H, int W) {
     constexpr int TW = 32, TH = 32;
     __shared__ T s_t[TH][TW + 1];
     const size_t plane = (size_t)H * W;
     const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
     const T* qy = f.q;
     const T* qx = f.q + plane;
-    // every load of the thread's four pixels first, then the arithmetic and
-    // the stores (loads after a store would wait for possible aliasing)
-    T qc_y[4], qc_x[4], qu[4], ql[4], vv[4], xh[4], hh[4], xo[4];
+    // every load of the thread's pixels first, then the arithmetic and the
+    // stores (loads after a store would wait for possible aliasing)
+    T qc_y[FIN_PPT], qc_x[FIN_PPT], qu[FIN_PPT], ql[FIN_PPT], vv[FIN_PPT], xh[FIN_PPT],
+        hh[FIN_PPT], xo[FIN_PPT];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < FIN_PPT; ++p) {
+        const int idx = (int)threadIdx.x + p * FIN_NT;
         const int li = idx / TW, lj = idx % TW;
         const int i = i0 + li, j = j0 + lj;
         const bool ok = i < H && j < W;
@@ -827,8 +831,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
         xo[p] = ok && (f.mode == 2 || f.mode == 4) ? f.x[g] : T(0);
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < FIN_PPT; ++p) {
+        const int idx = (int)threadIdx.x + p * FIN_NT;
         const int li = idx / TW, lj = idx % TW;
         const int i = i0 + li, j = j0 + lj;
         if (i >= H || j >= W) continue;
@@ -862,8 +866,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
     if (f.mode >= 2 && f.xbarT) {
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int idx = (int)threadIdx.x + p * 256;
+        for (int p = 0; p < FIN_PPT; ++p) {
+            const int idx = (int)threadIdx.x + p * FIN_NT;
             const int jj = idx / TH, ii = idx % TH;
             const int i = i0 + ii, j = j0 + jj;
             if (i < H && j < W) f.xbarT[(size_t)j * f.xbarT_ld + i] = s_t[ii][jj];
@@ -874,7 +878,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(Finalize<T> f, int H, int
 template <typename T>
 void launch_finalize(tvs_ctx* ctx, int H, int W, const Finalize<T>& f) {
     dim3 grid(div_up(W, 32), div_up(H, 32));
-    hipLaunchKernelGGL((finalize_kernel<T>), grid, dim3(256), 0, ctx->stream, f, H, W);
+    hipLaunchKernelGGL((finalize_kernel<T>), grid, dim3(FIN_NT), 0, ctx->stream, f, H, W);
     TVS_LAUNCH_CHECK();
 }
 
