@@ -469,21 +469,24 @@ __device__ __forceinline__ void fgp_strip_tb(const FgpArgs<T>& a, int ty, int tx
     }
 }
 
-// Threads per tile workgroup: tiles of 1024 pixels or more take 1024 threads
-// (a CU holds 16 waves of one tile instead of a quarter as many), smaller
-// tiles 256.  At 512^2 (256 tiles of 32 x 32) this lets the large tiles,
-// whose halo recomputation is 2.25x instead of 4x for 16 x 16, fill the chip.
-template <int BW, int BH>
+// Threads per tile workgroup: 1024 when 256 threads would each hold eight or
+// more region pixels, else 256.  At 512^2 (256 tiles of 32 x 32) the deep
+// 32 x 32 tiles, whose halo recomputation is 2.25x instead of 4x for
+// 16 x 16, then run 16 waves per CU instead of 4 and fill the chip; the
+// shallow ones keep 256 threads, which are faster at HBM-bound sizes (more
+// loads in flight per thread).
+template <int BW, int BH, int TS>
 struct FgpTileThreads {
-    static constexpr int value = (BW * BH >= 1024) ? 1024 : 256;
+    static constexpr int value =
+        (((BW + 2 * TS) * (BH + 2 * TS) + 255) / 256 >= 8) ? 1024 : 256;
 };
 
 template <typename T, int BW, int BH, int TS>
-__global__ __launch_bounds__((FgpTileThreads<BW, BH>::value)) void fgp_tb_kernel(FgpArgs<T> a) {
+__global__ __launch_bounds__((FgpTileThreads<BW, BH, TS>::value)) void fgp_tb_kernel(FgpArgs<T> a) {
     if (a.run_flag && *a.run_flag == 0) return;  // uniform across the grid
     const int gx = div_up(a.W, BW);
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    fgp_tile<T, BW, BH, TS, FgpTileThreads<BW, BH>::value>(a, t / gx, t % gx);
+    fgp_tile<T, BW, BH, TS, FgpTileThreads<BW, BH, TS>::value>(a, t / gx, t % gx);
 }
 
 template <typename T, int RC>
@@ -552,12 +555,12 @@ __device__ __forceinline__ FgpArgs<T> batched_tile(const FgpBatchArgs<T>& a, int
 }
 
 template <typename T, int BW, int BH, int TS>
-__global__ __launch_bounds__((FgpTileThreads<BW, BH>::value)) void fgp_tb_batched_kernel(
+__global__ __launch_bounds__((FgpTileThreads<BW, BH, TS>::value)) void fgp_tb_batched_kernel(
     FgpBatchArgs<T> a) {
     const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // one block per tile
     int ty, tx;
     const FgpArgs<T> f = batched_tile<T, BW>(a, b, ty, tx);
-    fgp_tile<T, BW, BH, TS, FgpTileThreads<BW, BH>::value>(f, ty, tx);
+    fgp_tile<T, BW, BH, TS, FgpTileThreads<BW, BH, TS>::value>(f, ty, tx);
 }
 
 template <typename T, int RC>
@@ -601,7 +604,7 @@ static void launch_fgp_variant(int vi, const FgpArgs<T>& a, hipStream_t st) {
 #define TVS_FGPV(BW_, BH_, TS_)                                                            \
     if (!V.strip && V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                    \
         hipLaunchKernelGGL((fgp_tb_kernel<T, BW_, BH_, TS_>), grid,                       \
-                           dim3(FgpTileThreads<BW_, BH_>::value), 0, st, a);               \
+                           dim3(FgpTileThreads<BW_, BH_, TS_>::value), 0, st, a);               \
         return;                                                                            \
     }
     TVS_FGPV(32, 32, 1) TVS_FGPV(32, 32, 2) TVS_FGPV(32, 32, 4) TVS_FGPV(32, 32, 8)
@@ -722,7 +725,7 @@ static void launch_fgp_batched_variant(int vi, const FgpBatchArgs<T>& a, int blo
 #define TVS_FGPB(BW_, BH_, TS_)                                                                  \
     if (!V.strip && V.bw == BW_ && V.bh == BH_ && V.ts == TS_) {                                          \
         hipLaunchKernelGGL((fgp_tb_batched_kernel<T, BW_, BH_, TS_>), dim3(blocks),              \
-                           dim3(FgpTileThreads<BW_, BH_>::value), 0, st, a);                     \
+                           dim3(FgpTileThreads<BW_, BH_, TS_>::value), 0, st, a);                     \
         return;                                                                                  \
     }
     TVS_FGPB(32, 32, 1) TVS_FGPB(32, 32, 2) TVS_FGPB(32, 32, 4) TVS_FGPB(32, 32, 8)
