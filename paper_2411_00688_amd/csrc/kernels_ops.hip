@@ -314,8 +314,12 @@ struct BlurArgs {
 
 // (A x)_{i,j} = sum_{a,c} k[a][c] x[(i - (a - kh/2)) mod H][(j - (c - kw/2)) mod W]
 // (A^T y)_{i,j} = sum_{a,c} k[a][c] y[(i + (a - kh/2)) mod H][(j + (c - kw/2)) mod W]
+// one pixel of the 32 x 32 output tile per thread: at 512^2 the 256 tiles
+// then give every CU 16 waves
+constexpr int BLUR_NT = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
+__global__ __launch_bounds__(BLUR_NT) void blur_kernel(BlurArgs<T> a) {
     constexpr int TW = 32, TH = 32, RMAX = 8;
     constexpr int LW = TW + 2 * RMAX, LH = TH + 2 * RMAX;
     __shared__ T s_x[LH][LW + 1];
@@ -325,9 +329,9 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
     const int rh = a.kh / 2, rw = a.kw / 2;
     const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
     const int tid = (int)threadIdx.x;
-    for (int idx = tid; idx < a.kh * a.kw; idx += 256) s_k[idx] = a.k[idx];
+    for (int idx = tid; idx < a.kh * a.kw; idx += BLUR_NT) s_k[idx] = a.k[idx];
     const int lh = TH + 2 * rh, lw = TW + 2 * rw;
-    for (int idx = tid; idx < lh * lw; idx += 256) {
+    for (int idx = tid; idx < lh * lw; idx += BLUR_NT) {
         const int li = idx / lw, lj = idx % lw;
         int gi = (i0 - rh + li) % H;
         if (gi < 0) gi += H;
@@ -337,8 +341,8 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = tid + p * 256;
+    for (int p = 0; p < (TW * TH) / BLUR_NT; ++p) {
+        const int idx = tid + p * BLUR_NT;
         const int li = idx / TW, lj = idx % TW;
         const int i = i0 + li, j = j0 + lj;
         if (i >= H || j >= W) continue;
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(256) void blur_kernel(BlurArgs<T> a) {
         }
     }
     if (a.mode == BLUR_PRIMAL && a.ps.pdhg && !a.ps.theta && a.ps.xbarT)
-        store_tile_transposed<T>(s_t, i0, j0, H, W, a.ps.xbarT, a.ps.xbarT_ld);
+        store_tile_transposed<T, BLUR_NT>(s_t, i0, j0, H, W, a.ps.xbarT, a.ps.xbarT_ld);
 }
 
 template <typename T>
@@ -380,8 +384,8 @@ static BlurArgs<T> blur_args(const tvs_op* op, bool adjoint) {
 
 template <typename T>
 static void launch_blur_args(tvs_ctx* ctx, const BlurArgs<T>& a) {
-    hipLaunchKernelGGL((blur_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)), dim3(256), 0,
-                       ctx->stream, a);
+    hipLaunchKernelGGL((blur_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)), dim3(BLUR_NT),
+                       0, ctx->stream, a);
     TVS_LAUNCH_CHECK();
 }
 
