@@ -191,15 +191,19 @@ __device__ __forceinline__ void store_tile_transposed(T (*s_t)[33], int i0, int 
 
 // ---------------------------------------------------------------- identity
 // s = x - b (ProxSkip gradient, from_y = 0) or s = y (PDHGSkip A^T y, from_y = 1)
+// 32 x 32 pixel tiles with one pixel per thread: at 512^2 the 256 tiles give
+// every CU 16 waves
+constexpr int TILE_NT = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void identity_step_kernel(int H, int W, const T* src,
+__global__ __launch_bounds__(TILE_NT) void identity_step_kernel(int H, int W, const T* src,
                                                             const T* b, PrimalStep<T> ps,
                                                             int from_y) {
     __shared__ T s_t[32][33];
     const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < 1024 / TILE_NT; ++p) {
+        const int idx = (int)threadIdx.x + p * TILE_NT;
         const int li = idx / 32, lj = idx % 32;
         const int i = i0 + li, j = j0 + lj;
         if (i < H && j < W) {
@@ -209,19 +213,19 @@ __global__ __launch_bounds__(256) void identity_step_kernel(int H, int W, const 
         }
     }
     if (ps.pdhg && !ps.theta && ps.xbarT)
-        store_tile_transposed<T>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
+        store_tile_transposed<T, TILE_NT>(s_t, i0, j0, H, W, ps.xbarT, ps.xbarT_ld);
 }
 
 template <typename T>
 void launch_identity_step(tvs_ctx* ctx, int H, int W, const T* b, const PrimalStep<T>& ps) {
-    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256),
+    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(TILE_NT),
                        0, ctx->stream, H, W, (const T*)nullptr, b, ps, 0);
     TVS_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_identity_adj_step(tvs_ctx* ctx, int H, int W, const T* y, const PrimalStep<T>& ps) {
-    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256),
+    hipLaunchKernelGGL((identity_step_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(TILE_NT),
                        0, ctx->stream, H, W, y, (const T*)nullptr, ps, 1);
     TVS_LAUNCH_CHECK();
 }
@@ -781,12 +785,12 @@ void launch_joseph_fwd(tvs_ctx* ctx, const tvs_op* op, const T* x, const T* xT, 
 // Both zero-padded copies of x (row-major and transposed), pads included.
 // 32 x 32 tiles through LDS; the pad columns are written by the edge tiles.
 template <typename T>
-__global__ __launch_bounds__(256) void pad_copy_kernel(int H, int W, const T* x, T* xp, T* xTp) {
+__global__ __launch_bounds__(TILE_NT) void pad_copy_kernel(int H, int W, const T* x, T* xp, T* xTp) {
     __shared__ T t[32][33];
     const int i0 = (int)blockIdx.y * 32, j0 = (int)blockIdx.x * 32;
     const int ld = W + 2 * JPAD, ldT = H + 2 * JPAD;
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < 1024 / TILE_NT; ++p) {
+        const int idx = (int)threadIdx.x + p * TILE_NT;
         const int li = idx / 32, lj = idx % 32;
         const int i = i0 + li, j = j0 + lj;
         if (i < H && j < W) {
@@ -797,7 +801,7 @@ __global__ __launch_bounds__(256) void pad_copy_kernel(int H, int W, const T* x,
     }
     // pads of the row-major copy: columns -JPAD..-1 and W..W+JPAD-1 of rows i
     if (blockIdx.x == 0) {
-        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += 256) {
+        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += TILE_NT) {
             const int li = idx / (2 * JPAD), k = idx % (2 * JPAD);
             const int i = i0 + li;
             if (i < H) {
@@ -807,14 +811,14 @@ __global__ __launch_bounds__(256) void pad_copy_kernel(int H, int W, const T* x,
         }
     }
     __syncthreads();
-    for (int p = 0; p < 4; ++p) {
-        const int idx = (int)threadIdx.x + p * 256;
+    for (int p = 0; p < 1024 / TILE_NT; ++p) {
+        const int idx = (int)threadIdx.x + p * TILE_NT;
         const int jj = idx / 32, ii = idx % 32;
         if (i0 + ii < H && j0 + jj < W) xTp[(size_t)(j0 + jj) * ldT + i0 + ii] = t[ii][jj];
     }
     // pads of the transposed copy: columns -JPAD..-1 and H..H+JPAD-1 of rows j
     if (blockIdx.y == 0) {
-        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += 256) {
+        for (int idx = (int)threadIdx.x; idx < 32 * 2 * JPAD; idx += TILE_NT) {
             const int lj = idx / (2 * JPAD), k = idx % (2 * JPAD);
             const int j = j0 + lj;
             if (j < W) {
@@ -827,7 +831,7 @@ __global__ __launch_bounds__(256) void pad_copy_kernel(int H, int W, const T* x,
 
 template <typename T>
 void launch_pad_copy(tvs_ctx* ctx, int H, int W, const T* x, T* xp, T* xTp) {
-    hipLaunchKernelGGL((pad_copy_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(256), 0,
+    hipLaunchKernelGGL((pad_copy_kernel<T>), dim3(div_up(W, 32), div_up(H, 32)), dim3(TILE_NT), 0,
                        ctx->stream, H, W, x, xp, xTp);
     TVS_LAUNCH_CHECK();
 }
