@@ -322,7 +322,11 @@ struct BlurArgs {
 // then give every CU 16 waves
 constexpr int BLUR_NT = 1024;
 
-template <typename T>
+// KS > 0: a KS x KS kernel known at compile time (the loops unroll and the
+// weights, the same for every thread, come through scalar loads instead of
+// LDS); KS = 0: any odd size up to 17, read from LDS.  Same products in the
+// same order either way.
+template <typename T, int KS>
 __global__ __launch_bounds__(BLUR_NT) void blur_kernel(BlurArgs<T> a) {
     constexpr int TW = 32, TH = 32, RMAX = 8;
     constexpr int LW = TW + 2 * RMAX, LH = TH + 2 * RMAX;
@@ -330,10 +334,13 @@ __global__ __launch_bounds__(BLUR_NT) void blur_kernel(BlurArgs<T> a) {
     __shared__ T s_k[17 * 17];
     __shared__ T s_t[32][33];
     const int H = a.H, W = a.W;
-    const int rh = a.kh / 2, rw = a.kw / 2;
+    const int kh = KS ? KS : a.kh, kw = KS ? KS : a.kw;
+    const int rh = kh / 2, rw = kw / 2;
     const int i0 = (int)blockIdx.y * TH, j0 = (int)blockIdx.x * TW;
     const int tid = (int)threadIdx.x;
-    for (int idx = tid; idx < a.kh * a.kw; idx += BLUR_NT) s_k[idx] = a.k[idx];
+    if (!KS)
+        for (int idx = tid; idx < kh * kw; idx += BLUR_NT) s_k[idx] = a.k[idx];
+    const T* kw_src = KS ? a.k : s_k;
     const int lh = TH + 2 * rh, lw = TW + 2 * rw;
     for (int idx = tid; idx < lh * lw; idx += BLUR_NT) {
         const int li = idx / lw, lj = idx % lw;
@@ -352,12 +359,16 @@ __global__ __launch_bounds__(BLUR_NT) void blur_kernel(BlurArgs<T> a) {
         if (i >= H || j >= W) continue;
         T s = T(0);
         if (!a.adjoint) {
-            for (int r = 0; r < a.kh; ++r)
-                for (int c = 0; c < a.kw; ++c)
-                    s += s_k[r * a.kw + c] * s_x[li + 2 * rh - r][lj + 2 * rw - c];
+#pragma unroll
+            for (int r = 0; r < kh; ++r)
+#pragma unroll
+                for (int c = 0; c < kw; ++c)
+                    s += kw_src[r * kw + c] * s_x[li + 2 * rh - r][lj + 2 * rw - c];
         } else {
-            for (int r = 0; r < a.kh; ++r)
-                for (int c = 0; c < a.kw; ++c) s += s_k[r * a.kw + c] * s_x[li + r][lj + c];
+#pragma unroll
+            for (int r = 0; r < kh; ++r)
+#pragma unroll
+                for (int c = 0; c < kw; ++c) s += kw_src[r * kw + c] * s_x[li + r][lj + c];
         }
         const size_t g = (size_t)i * W + j;
         if (a.mode == BLUR_STORE) {
@@ -388,8 +399,11 @@ static BlurArgs<T> blur_args(const tvs_op* op, bool adjoint) {
 
 template <typename T>
 static void launch_blur_args(tvs_ctx* ctx, const BlurArgs<T>& a) {
-    hipLaunchKernelGGL((blur_kernel<T>), dim3(div_up(a.W, 32), div_up(a.H, 32)), dim3(BLUR_NT),
-                       0, ctx->stream, a);
+    const dim3 grid(div_up(a.W, 32), div_up(a.H, 32));
+    if (a.kh == 9 && a.kw == 9)
+        hipLaunchKernelGGL((blur_kernel<T, 9>), grid, dim3(BLUR_NT), 0, ctx->stream, a);
+    else
+        hipLaunchKernelGGL((blur_kernel<T, 0>), grid, dim3(BLUR_NT), 0, ctx->stream, a);
     TVS_LAUNCH_CHECK();
 }
 
