@@ -74,6 +74,20 @@ def test_f64_large_image_matches_oracle(ctx, eps):
     assert rel_l2(host(h), ref["h"]) < 1e-9
 
 
+@pytest.mark.parametrize("eps", [0.0, 0.05])
+def test_f64_one_tile_per_cu_path_matches_oracle(ctx, eps):
+    """520 x 500 has between one and two 32 x 32 tiles per CU: the path with
+    32 x 32 tiles, 8 steps per launch and 1024-thread workgroups."""
+    b = as_input(noisy(520, 500, 17), F64)
+    alpha, p, K = 0.3, 0.3, 21
+    step = 1.0 / (8.0 + eps / alpha)
+    ref = O.dual_rof_proxskip(b, alpha, eps, step, p, K, seed=12)
+    q, h, r = run_gpu(ctx, b, alpha, eps, step, p, K, F64, seed=12)
+    assert np.array_equal(r["theta"], ref["theta"])
+    assert rel_l2(host(q), ref["q"]) < 1e-10
+    assert rel_l2(host(h), ref["h"]) < 1e-9
+
+
 def test_f32_8192_sampled_windows(ctx):
     """The 8192^2 float32 run the benchmark times (32 x 32 tiles, 8 steps per
     launch), checked on sampled windows: after K steps a pixel depends only
